@@ -1,0 +1,201 @@
+/*
+ * lbmletkf.h -- C ABI of the MI355X (gfx950) forecast-analysis cycle of
+ * LBM-LETKF (Hasegawa et al., "Continuous data assimilation of large eddy
+ * simulation by lattice Boltzmann method and local ensemble transform Kalman
+ * filter").
+ *
+ * The library runs the continuous-DA workflow of Sec. 3 on one GPU:
+ *   (ii) forecast: every ensemble member advances s steps of the D2Q9
+ *        lattice Boltzmann equation with BGK relaxation, Smagorinsky eddy
+ *        viscosity and a body force (Sec. 2);
+ *  (iii) observation: y_m = H(x_m), the macroscopic variables (u, v) or
+ *        (rho, u, v) at the observation nodes (Sec. 3, state and
+ *        observation vectors);
+ *   (iv) analysis: the LETKF of Sec. 3.2.1 with R-localization by the
+ *        Gaspari-Cohn weight and multiplicative inflation (Sec. 3.2.2),
+ *        solved independently at every grid node and applied directly to
+ *        the nine populations.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers named d_* are DEVICE pointers; all other pointers are host.
+ * Every device buffer is allocated and owned by the caller; the library never
+ * allocates or frees device memory.  `stream` is a hipStream_t passed as
+ * void* (NULL = the default stream).  All calls are stream-ordered and return
+ * without waiting for the GPU, except lbmletkf_create (which uploads its
+ * tables and waits once) and lbmletkf_profile_collect.
+ *
+ * Lattice units: dx = dt = c = 1.  D2Q9 velocity order
+ *   0:(0,0) 1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1) 5:(1,1) 6:(-1,-1) 7:(1,-1) 8:(-1,1).
+ *
+ * State layouts (FP64, members x 9 x ny x nx, x fastest):
+ *   canonical  f[m][a][y][x] = f_a(x, y) of member m, the pre-collision
+ *              population of the lattice Boltzmann equation -- the state
+ *              vector x(xi) = [f_0 .. f_8] the LETKF updates.
+ *   storage    the layout the kernels keep between calls: slot [m][a][y][x]
+ *              holds the canonical f_a of node (x + c_ax, y + c_ay), i.e. the
+ *              post-collision value streamed by a pull step.  Convert with
+ *              lbmletkf_import / lbmletkf_export.
+ * Observation vector index q = nvar * k + var, k = observation point,
+ * var = (u, v) for nvar = 2 and (rho, u, v) for nvar = 3.
+ *
+ * Errors: every function returns a status and never aborts.  Arguments are
+ * validated on the host before any launch; a failed launch maps to
+ * LBMLETKF_EHIP.  lbmletkf_last_error() gives a thread-local message.
+ * A context is not thread-safe; two contexts may share a device.
+ */
+#ifndef LBMLETKF_H
+#define LBMLETKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBMLETKF_OK = 0,
+    LBMLETKF_EINVAL = -1,      /* invalid parameter value */
+    LBMLETKF_ESHAPE = -2,      /* sizes the kernels cannot take */
+    LBMLETKF_EHIP = -3,        /* a HIP runtime call or launch failed */
+    LBMLETKF_ENONFINITE = -4,  /* non-finite value found by the diagnostics */
+    LBMLETKF_EDIVERGED = -5,   /* spread or RMSE above the divergence limit */
+    LBMLETKF_EEIG = -6,        /* eigensolver did not converge */
+    LBMLETKF_EWORKSPACE = -7,  /* workspace missing, misaligned or too small */
+    LBMLETKF_EUNSUPPORTED = -8 /* valid request this build does not implement */
+} lbmletkf_status;
+
+/* Storage precision of the populations. */
+typedef enum { LBMLETKF_F64 = 0 } lbmletkf_storage;
+
+/* Which eigenproblem the analysis solves (both give the same analysis):
+ *   ENSEMBLE     the M x M matrix (M-1)/beta I + dY^T R_loc^-1 dY of Sec. 3.2.2;
+ *   OBSERVATION  its l x l dual Z Z^T, Z = R_loc^-1/2 dY (l = local
+ *                observations), whose eigenpairs give those of the M x M
+ *                matrix: eigenvalue (M-1)/beta + lambda_i with vector
+ *                Z^T u_i / sqrt(lambda_i), and (M-1)/beta on the rest;
+ *   AUTO         the smaller of the two. */
+typedef enum {
+    LBMLETKF_ROUTE_AUTO = 0,
+    LBMLETKF_ROUTE_ENSEMBLE = 1,
+    LBMLETKF_ROUTE_OBSERVATION = 2
+} lbmletkf_route;
+
+/* Forecast model parameters (Sec. 2). */
+typedef struct {
+    int32_t nx, ny;    /* grid, doubly periodic; nx, ny >= 3 */
+    int32_t members;   /* ensemble size M, 1..64 (M >= 2 for an analysis) */
+    double tau0;       /* molecular relaxation time, > 1/2 (nu = (tau0 - 1/2)/3) */
+    double cs;         /* Smagorinsky constant C_s >= 0, filter width = dx */
+    double mu;         /* linear friction coefficient >= 0 (force -mu u) */
+    int32_t storage;   /* lbmletkf_storage */
+} lbmletkf_lbm_params;
+
+/* Observing network and analysis parameters (Sec. 3.2, Sec. 4.3). */
+typedef struct {
+    int32_t n_points;        /* observation points, >= 1 */
+    const int32_t* points;   /* host, [n_points][2] = (x, y) node indices; copied */
+    int32_t nvar;            /* 2: (u, v); 3: (rho, u, v) */
+    double sigma[3];         /* observation-error std per variable (> 0), var order */
+    double d_cut;            /* Gaspari-Cohn cutoff in cells; <= 0 or inf: no localization */
+    double beta;             /* multiplicative inflation > 0 */
+    int32_t route;           /* lbmletkf_route */
+} lbmletkf_obs_params;
+
+/* Size of the device workspace a context needs (bytes, 256-byte aligned base). */
+lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
+                                         const lbmletkf_obs_params* obs, size_t* bytes);
+
+/* Create a context.  d_force: device [2][ny][nx] external acceleration
+ * (F_x, F_y) or NULL for none; it is copied into the workspace.  The
+ * workspace (caller-owned, >= lbmletkf_workspace_bytes) must stay valid until
+ * lbmletkf_destroy.  Builds the per-node local-observation table on the GPU
+ * (a4: observations with Gaspari-Cohn weight > 0) and waits for it. */
+lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
+                                const double* d_force, void* d_workspace, size_t bytes,
+                                void* stream, void** ctx_out);
+
+/* Free the host context (the workspace stays with the caller). */
+lbmletkf_status lbmletkf_destroy(void* ctx);
+
+/* Equilibrium state f^eq(rho, u) (Sec. 2 equilibrium) in storage layout.
+ * d_rho: [M][ny][nx] or NULL for rho = 1; d_uv: [M][2][ny][nx]. */
+lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const double* d_uv,
+                                          double* d_f, void* stream);
+
+/* canonical -> storage and storage -> canonical (buffers must not overlap). */
+lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, double* d_f, void* stream);
+lbmletkf_status lbmletkf_export(void* ctx, const double* d_f, double* d_canonical, void* stream);
+
+/* a1 -- forecast (Sec. 2 LBE): advance every member nsteps >= 0 steps of
+ * fused pull-stream + collide, in place on d_f (storage layout; the
+ * workspace holds the ping-pong partner). */
+lbmletkf_status lbm_ensemble_step(void* ctx, double* d_f, int32_t nsteps, void* stream);
+
+/* a2 -- observation operator y = H x (Sec. 3): d_yf[M][nvar * n_points]. */
+lbmletkf_status observe(void* ctx, const double* d_f, double* d_yf, void* stream);
+
+/* a3..a8 -- LETKF analysis (Sec. 3.2.1, Sec. 3.2.2), in place on d_f:
+ * ensemble statistics of d_yf against d_yo[nvar * n_points], then at every
+ * node the localized ensemble-space problem, its symmetric
+ * eigendecomposition, w_bar, dW = [(M-1) P~a]^(1/2) and
+ * x_m^a = x_bar + dX (w_bar + dW[:, m]) applied to the nine populations. */
+lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const double* d_yo,
+                              void* stream);
+
+/* a9 -- ensemble diagnostics into d_diag[LBMLETKF_DIAG_LEN]: RMSE of the
+ * ensemble-mean velocity against d_truth_uv ([2][ny][nx]; Sec. 4.3.1), spread,
+ * non-finite count, min/max density.  d_truth_uv may be NULL (RMSE = 0). */
+#define LBMLETKF_DIAG_LEN 8
+#define LBMLETKF_DIAG_RMSE 0
+#define LBMLETKF_DIAG_SPREAD 1
+#define LBMLETKF_DIAG_NONFINITE 2
+#define LBMLETKF_DIAG_RHO_MIN 3
+#define LBMLETKF_DIAG_RHO_MAX 4
+lbmletkf_status lbmletkf_diagnostics(void* ctx, const double* d_f, const double* d_truth_uv,
+                                     double* d_diag, void* stream);
+
+/* a10 -- one forecast-analysis cycle (Sec. 3 workflow (ii)-(iv)):
+ * lbm_ensemble_step(nsteps) -> observe -> letkf_analyze.  d_yo: this
+ * cycle's observations.  If d_diag is not NULL it receives the forecast
+ * diagnostics in d_diag[0..7] and the analysis diagnostics in d_diag[8..15]
+ * (d_truth_uv as in lbmletkf_diagnostics). */
+lbmletkf_status run_cycle(void* ctx, double* d_f, int32_t nsteps, const double* d_yo,
+                          const double* d_truth_uv, double* d_diag, void* stream);
+
+/* rho, u, v of every node of every member: d_out[M][3][ny][nx]. */
+lbmletkf_status lbmletkf_moments(void* ctx, const double* d_f, double* d_out, void* stream);
+
+/* Synthetic observations y^o_q = y_q + sigma_q * eps_q for q < n (OSSE,
+ * Sec. 4.3); all three arrays and d_yo are device [n]. */
+lbmletkf_status lbmletkf_synth_obs(const double* d_y, const double* d_eps, const double* d_sigma,
+                                   double* d_yo, int32_t n, void* stream);
+
+/* Host-only plan (no GPU call): the largest number of observation points in
+ * any node's localization support (squared distance < (2 d_cut)^2), the
+ * eigenproblem size the analysis will use and its route after AUTO. */
+lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
+                              int32_t* max_local_points, int32_t* eig_size, int32_t* route);
+
+/* Introspection: local-observation points per node (max over nodes), the
+ * eigenproblem size the analysis uses and its route (after AUTO). */
+lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig_size,
+                              int32_t* route);
+
+/* Per-stage GPU timing with HIP events on the launch stream.  When enabled,
+ * every launch is bracketed by an event pair; lbmletkf_profile_collect waits
+ * for them and returns, per stage, the summed milliseconds and launch counts,
+ * then clears the record.  Stages: 0 stream-collide, 1 observe, 2 obs
+ * statistics, 3 analysis, 4 diagnostics. */
+#define LBMLETKF_NSTAGES 5
+lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable);
+lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts);
+
+const char* lbmletkf_status_string(int32_t status);
+const char* lbmletkf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMLETKF_H */

@@ -3,17 +3,15 @@
 The compute path is the C-ABI library ``liblbmletkf.so`` (hand-written HIP
 kernels for gfx950, declared in ``include/lbmletkf.h``); ``binding`` is its
 thin ctypes wrapper.  ``inputs`` holds the seeded synthetic input generators.
-The binding is imported lazily so that importing the package (for example to
-reach ``inputs``) needs neither a GPU nor the built library.
+Submodules are imported on first use so that importing the package (for
+example to reach ``inputs``) needs neither a GPU nor the built library.
 """
-__all__ = ["inputs", "binding"]
+import importlib
+
+__all__ = ["inputs", "binding", "build"]
 
 
 def __getattr__(name):
-    if name == "binding":
-        from . import binding as _b
-        return _b
-    if name == "inputs":
-        from . import inputs as _i
-        return _i
+    if name in __all__:
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

@@ -1,0 +1,317 @@
+"""Thin ctypes binding of liblbmletkf.so (declared in include/lbmletkf.h).
+
+Argument marshalling only: every step of the forecast-analysis cycle runs in
+the library's HIP kernels.  Device buffers are torch CUDA tensors (float64,
+contiguous) and launches go to torch's current stream.  If the library is
+not built, loading fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch  # imported before the library so that one HIP runtime is shared
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmletkf.so")
+
+LBMLETKF_OK = 0
+DIAG_LEN = 8
+NSTAGES = 5
+STAGES = ("stream_collide", "observe", "obs_stats", "analysis", "diagnostics")
+ROUTE_AUTO, ROUTE_ENSEMBLE, ROUTE_OBSERVATION = 0, 1, 2
+
+_c_int32 = ctypes.c_int32
+_c_double = ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [("nx", _c_int32), ("ny", _c_int32), ("members", _c_int32),
+                ("tau0", _c_double), ("cs", _c_double), ("mu", _c_double),
+                ("storage", _c_int32)]
+
+
+class ObsParams(ctypes.Structure):
+    _fields_ = [("n_points", _c_int32), ("points", ctypes.POINTER(_c_int32)),
+                ("nvar", _c_int32), ("sigma", _c_double * 3), ("d_cut", _c_double),
+                ("beta", _c_double), ("route", _c_int32)]
+
+
+class LbmLetkfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lbmletkf status {status}: {msg}")
+        self.status = status
+
+
+# every symbol include/lbmletkf.h declares, with (restype, argtypes)
+SIGNATURES = {
+    "lbmletkf_workspace_bytes": (_c_int32, [ctypes.POINTER(LbmParams), ctypes.POINTER(ObsParams),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmletkf_create": (_c_int32, [ctypes.POINTER(LbmParams), ctypes.POINTER(ObsParams), _vp, _vp,
+                                   ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "lbmletkf_destroy": (_c_int32, [_vp]),
+    "lbmletkf_init_equilibrium": (_c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "lbmletkf_import": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "lbmletkf_export": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "lbm_ensemble_step": (_c_int32, [_vp, _vp, _c_int32, _vp]),
+    "observe": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "letkf_analyze": (_c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "lbmletkf_diagnostics": (_c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "run_cycle": (_c_int32, [_vp, _vp, _c_int32, _vp, _vp, _vp, _vp]),
+    "lbmletkf_moments": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "lbmletkf_synth_obs": (_c_int32, [_vp, _vp, _vp, _vp, _c_int32, _vp]),
+    "lbmletkf_plan": (_c_int32, [ctypes.POINTER(LbmParams), ctypes.POINTER(ObsParams),
+                                 ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32),
+                                 ctypes.POINTER(_c_int32)]),
+    "lbmletkf_info": (_c_int32, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32),
+                                 ctypes.POINTER(_c_int32)]),
+    "lbmletkf_set_profiling": (_c_int32, [_vp, _c_int32]),
+    "lbmletkf_profile_collect": (_c_int32, [_vp, ctypes.POINTER(_c_double),
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    "lbmletkf_status_string": (ctypes.c_char_p, [_c_int32]),
+    "lbmletkf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2308_03972_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != LBMLETKF_OK:
+        msg = load().lbmletkf_last_error().decode(errors="replace")
+        raise LbmLetkfError(status, msg)
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: Optional[torch.Tensor], numel: Optional[int] = None, name: str = "tensor"):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# C entry points under their own names
+# ---------------------------------------------------------------------------
+def lbm_ensemble_step(ctx: "Context", f: torch.Tensor, nsteps: int, stream=None) -> None:
+    _check(load().lbm_ensemble_step(ctx.handle, _dev(f, ctx.state_numel, "f"), int(nsteps),
+                                    _stream(stream)))
+
+
+def observe(ctx: "Context", f: torch.Tensor, yf: torch.Tensor, stream=None) -> None:
+    _check(load().observe(ctx.handle, _dev(f, ctx.state_numel, "f"),
+                          _dev(yf, ctx.members * ctx.n_obs, "yf"), _stream(stream)))
+
+
+def letkf_analyze(ctx: "Context", f: torch.Tensor, yf: torch.Tensor, yo: torch.Tensor,
+                  stream=None) -> None:
+    _check(load().letkf_analyze(ctx.handle, _dev(f, ctx.state_numel, "f"),
+                                _dev(yf, ctx.members * ctx.n_obs, "yf"),
+                                _dev(yo, ctx.n_obs, "yo"), _stream(stream)))
+
+
+def run_cycle(ctx: "Context", f: torch.Tensor, nsteps: int, yo: torch.Tensor,
+              truth_uv: Optional[torch.Tensor] = None, diag: Optional[torch.Tensor] = None,
+              stream=None) -> None:
+    _check(load().run_cycle(ctx.handle, _dev(f, ctx.state_numel, "f"), int(nsteps),
+                            _dev(yo, ctx.n_obs, "yo"), _dev(truth_uv, 2 * ctx.plane, "truth_uv"),
+                            _dev(diag, 2 * DIAG_LEN, "diag"), _stream(stream)))
+
+
+def plan(nx: int, ny: int, members: int, points, nvar: int, sigma: Sequence[float],
+         d_cut: float, beta: float, tau0: float = 0.6, cs: float = 0.1, mu: float = 0.0,
+         route: int = ROUTE_AUTO) -> Tuple[int, int, int]:
+    """Host-only: (max local points, eigenproblem size, route) -- no GPU needed."""
+    lbm, obs, _keep = _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta,
+                              route)
+    a, b, c = _c_int32(), _c_int32(), _c_int32()
+    _check(load().lbmletkf_plan(ctypes.byref(lbm), ctypes.byref(obs), ctypes.byref(a),
+                                ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def workspace_bytes(nx: int, ny: int, members: int, points, nvar: int, sigma: Sequence[float],
+                    d_cut: float, beta: float, tau0: float = 0.6, cs: float = 0.1,
+                    mu: float = 0.0, route: int = ROUTE_AUTO) -> int:
+    """Host-only: bytes of device workspace a context needs."""
+    lbm, obs, _keep = _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta,
+                              route)
+    n = ctypes.c_size_t(0)
+    _check(load().lbmletkf_workspace_bytes(ctypes.byref(lbm), ctypes.byref(obs), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta, route):
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 2))
+    lbm = LbmParams(int(nx), int(ny), int(members), float(tau0), float(cs), float(mu), 0)
+    sig = list(sigma) + [1.0] * (3 - len(sigma))
+    dc = float(d_cut) if math.isfinite(d_cut) else 0.0
+    obs = ObsParams(len(pts), pts.ctypes.data_as(ctypes.POINTER(_c_int32)), int(nvar),
+                    (_c_double * 3)(*sig), dc, float(beta), int(route))
+    return lbm, obs, pts
+
+
+def synth_obs(y: torch.Tensor, eps: torch.Tensor, sigma: torch.Tensor, stream=None) -> torch.Tensor:
+    n = y.numel()
+    yo = torch.empty_like(y)
+    _check(load().lbmletkf_synth_obs(_dev(y, n, "y"), _dev(eps, n, "eps"), _dev(sigma, n, "sigma"),
+                                     _dev(yo, n, "yo"), n, _stream(stream)))
+    return yo
+
+
+class Context:
+    """One ensemble (M members on an nx x ny grid) with its observing network.
+
+    Owns the device workspace (a torch uint8 tensor) and the library context.
+    """
+
+    def __init__(self, nx: int, ny: int, members: int, tau0: float, cs: float,
+                 points, nvar: int, sigma: Sequence[float], d_cut: float, beta: float,
+                 mu: float = 0.0, force: Optional[torch.Tensor] = None,
+                 route: int = ROUTE_AUTO, device: str = "cuda"):
+        lib = load()
+        self.nx, self.ny, self.members, self.nvar = int(nx), int(ny), int(members), int(nvar)
+        self.plane = self.nx * self.ny
+        self.state_numel = self.members * 9 * self.plane
+        self.points = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 2))
+        self.n_points = len(self.points)
+        self.n_obs = self.n_points * self.nvar
+        self.device = torch.device(device)
+        self._lbm, self._obs, self.points = _params(self.nx, self.ny, self.members, tau0, cs, mu,
+                                                    self.points, self.nvar, sigma, d_cut, beta,
+                                                    route)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.lbmletkf_workspace_bytes(ctypes.byref(self._lbm), ctypes.byref(self._obs),
+                                            ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._force = None
+        if force is not None:
+            self._force = force
+        h = _vp()
+        _check(lib.lbmletkf_create(ctypes.byref(self._lbm), ctypes.byref(self._obs),
+                                   _dev(force, 2 * self.plane, "force"), aligned,
+                                   ctypes.c_size_t(nbytes.value), _stream(None), ctypes.byref(h)))
+        self.handle = h
+        lmax, n, r = _c_int32(), _c_int32(), _c_int32()
+        _check(lib.lbmletkf_info(self.handle, ctypes.byref(lmax), ctypes.byref(n), ctypes.byref(r)))
+        self.max_local_points, self.eig_size, self.route = lmax.value, n.value, r.value
+
+    # -- construction from a configuration object (inputs.CycleConfig) --------
+    @classmethod
+    def from_config(cls, cfg, members: Optional[int] = None, force: Optional[torch.Tensor] = None,
+                    route: int = ROUTE_AUTO, points=None) -> "Context":
+        from . import inputs
+        pts = inputs.observation_points(cfg) if points is None else points
+        return cls(cfg.n, cfg.n, cfg.members if members is None else members, cfg.tau0, cfg.cs,
+                   pts, cfg.nvar, cfg.sigmas, cfg.d_cut, cfg.beta, mu=cfg.mu, force=force,
+                   route=route)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.lbmletkf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ---------------------------------------------------------------
+    def new_state(self) -> torch.Tensor:
+        return torch.empty((self.members, 9, self.ny, self.nx), dtype=torch.float64,
+                           device=self.device)
+
+    def init_equilibrium(self, uv: torch.Tensor, rho: Optional[torch.Tensor] = None,
+                         stream=None) -> torch.Tensor:
+        f = self.new_state()
+        _check(load().lbmletkf_init_equilibrium(
+            self.handle, _dev(rho, self.members * self.plane, "rho"),
+            _dev(uv, self.members * 2 * self.plane, "uv"), _dev(f), _stream(stream)))
+        return f
+
+    def import_canonical(self, canon: torch.Tensor, stream=None) -> torch.Tensor:
+        f = self.new_state()
+        _check(load().lbmletkf_import(self.handle, _dev(canon, self.state_numel, "canonical"),
+                                      _dev(f), _stream(stream)))
+        return f
+
+    def export_canonical(self, f: torch.Tensor, stream=None) -> torch.Tensor:
+        out = self.new_state()
+        _check(load().lbmletkf_export(self.handle, _dev(f, self.state_numel, "f"), _dev(out),
+                                      _stream(stream)))
+        return out
+
+    # -- the hot path ------------------------------------------------------------
+    def step(self, f: torch.Tensor, nsteps: int, stream=None) -> None:
+        lbm_ensemble_step(self, f, nsteps, stream)
+
+    def observe(self, f: torch.Tensor, yf: Optional[torch.Tensor] = None, stream=None):
+        if yf is None:
+            yf = torch.empty((self.members, self.n_obs), dtype=torch.float64, device=self.device)
+        observe(self, f, yf, stream)
+        return yf
+
+    def analyze(self, f: torch.Tensor, yf: torch.Tensor, yo: torch.Tensor, stream=None) -> None:
+        letkf_analyze(self, f, yf, yo, stream)
+
+    def run_cycle(self, f: torch.Tensor, nsteps: int, yo: torch.Tensor,
+                  truth_uv: Optional[torch.Tensor] = None, diag: Optional[torch.Tensor] = None,
+                  stream=None) -> None:
+        run_cycle(self, f, nsteps, yo, truth_uv, diag, stream)
+
+    # -- diagnostics ---------------------------------------------------------------
+    def diagnostics(self, f: torch.Tensor, truth_uv: Optional[torch.Tensor] = None,
+                    out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(DIAG_LEN, dtype=torch.float64, device=self.device)
+        _check(load().lbmletkf_diagnostics(self.handle, _dev(f, self.state_numel, "f"),
+                                           _dev(truth_uv, 2 * self.plane, "truth_uv"),
+                                           _dev(out, DIAG_LEN, "diag"), _stream(stream)))
+        return out
+
+    def moments(self, f: torch.Tensor, stream=None) -> torch.Tensor:
+        out = torch.empty((self.members, 3, self.ny, self.nx), dtype=torch.float64,
+                          device=self.device)
+        _check(load().lbmletkf_moments(self.handle, _dev(f, self.state_numel, "f"), _dev(out),
+                                       _stream(stream)))
+        return out
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(load().lbmletkf_set_profiling(self.handle, 1 if enable else 0))
+
+    def profile_collect(self) -> Tuple[np.ndarray, np.ndarray]:
+        ms = (_c_double * NSTAGES)()
+        cnt = (ctypes.c_int64 * NSTAGES)()
+        _check(load().lbmletkf_profile_collect(self.handle, ms, cnt))
+        return np.array(ms[:]), np.array(cnt[:])

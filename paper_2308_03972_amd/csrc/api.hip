@@ -1,0 +1,501 @@
+// C-ABI layer of liblbmletkf: argument validation, workspace carving, stream
+// ordering of the launches and per-stage timing.  Declarations and the
+// contract of every entry point are in include/lbmletkf.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmletkf.h"
+#include "common.h"
+
+using namespace lbmletkf;
+
+namespace lbmletkf {
+int analysis_lds_bytes(int n, int nz);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbmletkf_status fail(lbmletkf_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+lbmletkf_status hip_fail(hipError_t e, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return LBMLETKF_EHIP;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagBlocks = 512;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t fbuf, force, loc_pt, loc_g, pts, ybar, dY, dvec, K, yf, partial, counters, total;
+};
+
+struct Ctx {
+    lbmletkf_lbm_params lbm;
+    lbmletkf_obs_params obs;  // obs.points is not kept (device copy in the workspace)
+    LbmDims dims;
+    int nobs;
+    int lmax;
+    int route;  // 1 ensemble, 2 observation
+    int n_eig;
+    bool has_force;
+    char* ws;
+    Layout L;
+    // per-stage timing
+    bool profiling = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+
+    double* fbuf() const { return reinterpret_cast<double*>(ws + L.fbuf); }
+    const double* force() const {
+        return has_force ? reinterpret_cast<const double*>(ws + L.force) : nullptr;
+    }
+    int* loc_pt() const { return reinterpret_cast<int*>(ws + L.loc_pt); }
+    double* loc_g() const { return reinterpret_cast<double*>(ws + L.loc_g); }
+    int* pts() const { return reinterpret_cast<int*>(ws + L.pts); }
+    double* ybar() const { return reinterpret_cast<double*>(ws + L.ybar); }
+    double* dY() const { return reinterpret_cast<double*>(ws + L.dY); }
+    double* dvec() const { return reinterpret_cast<double*>(ws + L.dvec); }
+    double* K() const { return route == 2 ? reinterpret_cast<double*>(ws + L.K) : nullptr; }
+    double* yf() const { return reinterpret_cast<double*>(ws + L.yf); }
+    double* partial() const { return reinterpret_cast<double*>(ws + L.partial); }
+    int* counters() const { return reinterpret_cast<int*>(ws + L.counters); }
+};
+
+// RAII event pair around one launch when profiling is on.
+struct StageTimer {
+    Ctx* c;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(Ctx* ctx, int st, hipStream_t stream) : c(ctx), stage(st), s(stream) {
+        if (!c->profiling) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        c->recs.push_back({stage, a, b});
+    }
+};
+
+lbmletkf_status check_lbm(const lbmletkf_lbm_params* p) {
+    if (!p) return fail(LBMLETKF_EINVAL, "lbm params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(LBMLETKF_ESHAPE, "nx and ny must be >= 3");
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 28)
+        return fail(LBMLETKF_ESHAPE, "grid too large (nx*ny must be < 2^28)");
+    if (p->members < 1 || p->members > 64)
+        return fail(LBMLETKF_ESHAPE, "members must be in 1..64");
+    if (!(p->tau0 > 0.5) || !std::isfinite(p->tau0))
+        return fail(LBMLETKF_EINVAL, "tau0 must be finite and > 1/2");
+    if (!(p->cs >= 0.0) || !std::isfinite(p->cs)) return fail(LBMLETKF_EINVAL, "cs must be >= 0");
+    if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return fail(LBMLETKF_EINVAL, "mu must be >= 0");
+    if (p->storage != LBMLETKF_F64)
+        return fail(LBMLETKF_EUNSUPPORTED, "only FP64 storage is implemented");
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status check_obs(const lbmletkf_obs_params* o, const lbmletkf_lbm_params* p) {
+    if (!o) return fail(LBMLETKF_EINVAL, "obs params is NULL");
+    if (o->n_points < 1 || !o->points) return fail(LBMLETKF_EINVAL, "need >= 1 observation point");
+    if (o->nvar != 2 && o->nvar != 3) return fail(LBMLETKF_EINVAL, "nvar must be 2 or 3");
+    for (int v = 0; v < o->nvar; ++v)
+        if (!(o->sigma[v] > 0.0) || !std::isfinite(o->sigma[v]))
+            return fail(LBMLETKF_EINVAL, "sigma must be finite and > 0");
+    if (!(o->beta > 0.0) || !std::isfinite(o->beta))
+        return fail(LBMLETKF_EINVAL, "beta must be finite and > 0");
+    if (std::isnan(o->d_cut)) return fail(LBMLETKF_EINVAL, "d_cut is NaN");
+    if (o->route < 0 || o->route > 2) return fail(LBMLETKF_EINVAL, "unknown route");
+    for (int k = 0; k < o->n_points; ++k) {
+        const int x = o->points[2 * k], y = o->points[2 * k + 1];
+        if (x < 0 || x >= p->nx || y < 0 || y >= p->ny)
+            return fail(LBMLETKF_EINVAL, "observation point outside the grid");
+    }
+    if ((int64_t)o->n_points * o->nvar > 16384)
+        return fail(LBMLETKF_ESHAPE, "at most 16384 observations");
+    return LBMLETKF_OK;
+}
+
+bool infinite_cut(double d_cut) { return !(d_cut > 0.0) || std::isinf(d_cut); }
+
+// Largest number of observation points inside the localization support of
+// any node; the same criterion (squared distance < (2 d_cut)^2) as the GPU
+// table build, used only for sizing.
+int count_lmax(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o) {
+    if (infinite_cut(o->d_cut)) return o->n_points;
+    const double lim = 4.0 * o->d_cut * o->d_cut;
+    int best = 0;
+    std::vector<int> dxs(o->n_points);
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            int cnt = 0;
+            for (int k = 0; k < o->n_points; ++k) {
+                int dx = std::abs(x - o->points[2 * k]), dy = std::abs(y - o->points[2 * k + 1]);
+                dx = std::min(dx, p->nx - dx);
+                dy = std::min(dy, p->ny - dy);
+                if ((double)(dx * dx + dy * dy) < lim) ++cnt;
+            }
+            best = std::max(best, cnt);
+        }
+    return best;
+}
+
+int even_up(int n) { return (n + 1) & ~1; }
+
+// Choose the eigenproblem route and its instantiated size.
+lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, int lmax,
+                             int* route, int* n) {
+    const int nz = o->nvar * lmax;
+    const int nE = analysis_size_for(even_up(p->members));
+    const int nO = analysis_size_for(even_up(nz));
+    int r = o->route;
+    if (r == LBMLETKF_ROUTE_AUTO) {
+        if (nO == 0) r = LBMLETKF_ROUTE_ENSEMBLE;
+        else r = (nO < nE) ? LBMLETKF_ROUTE_OBSERVATION : LBMLETKF_ROUTE_ENSEMBLE;
+    }
+    const int sz = (r == LBMLETKF_ROUTE_OBSERVATION) ? nO : nE;
+    if (sz == 0)
+        return fail(LBMLETKF_EUNSUPPORTED,
+                    "observation route needs at most 64 local observations per node");
+    if (analysis_lds_bytes(sz, nz) > 65536)
+        return fail(LBMLETKF_EUNSUPPORTED, "too many local observations for the LDS budget");
+    *route = r;
+    *n = sz;
+    return LBMLETKF_OK;
+}
+
+Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, int lmax,
+                   int route) {
+    Layout L{};
+    const size_t plane = (size_t)p->nx * p->ny;
+    const size_t nobs = (size_t)o->n_points * o->nvar;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.fbuf = take(plane * 9 * p->members * sizeof(double));
+    L.force = take(plane * 2 * sizeof(double));
+    L.loc_pt = take(plane * std::max(lmax, 1) * sizeof(int));
+    L.loc_g = take(plane * std::max(lmax, 1) * sizeof(double));
+    L.pts = take((size_t)o->n_points * 2 * sizeof(int));
+    L.ybar = take(nobs * sizeof(double));
+    L.dY = take(nobs * p->members * sizeof(double));
+    L.dvec = take(nobs * sizeof(double));
+    L.K = take(route == 2 ? nobs * nobs * sizeof(double) : 0);
+    L.yf = take(nobs * p->members * sizeof(double));
+    L.partial = take((size_t)kDiagBlocks * 8 * sizeof(double));
+    L.counters = take(16 * sizeof(int));
+    L.total = off;
+    return L;
+}
+
+Ctx* as_ctx(void* c) { return reinterpret_cast<Ctx*>(c); }
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* lbmletkf_status_string(int32_t st) {
+    switch (st) {
+        case LBMLETKF_OK: return "ok";
+        case LBMLETKF_EINVAL: return "invalid argument";
+        case LBMLETKF_ESHAPE: return "unsupported shape";
+        case LBMLETKF_EHIP: return "HIP error";
+        case LBMLETKF_ENONFINITE: return "non-finite value";
+        case LBMLETKF_EDIVERGED: return "filter diverged";
+        case LBMLETKF_EEIG: return "eigensolver did not converge";
+        case LBMLETKF_EWORKSPACE: return "workspace missing or too small";
+        case LBMLETKF_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* lbmletkf_last_error(void) { return g_last_error.c_str(); }
+
+lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
+                                         const lbmletkf_obs_params* obs, size_t* bytes) {
+    lbmletkf_status st = check_lbm(lbm);
+    if (st) return st;
+    if ((st = check_obs(obs, lbm))) return st;
+    if (!bytes) return fail(LBMLETKF_EINVAL, "bytes is NULL");
+    const int lmax = count_lmax(lbm, obs);
+    int route = 0, n = 0;
+    if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
+    *bytes = make_layout(lbm, obs, lmax, route).total;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
+                              int32_t* max_local_points, int32_t* eig_size, int32_t* route) {
+    lbmletkf_status st = check_lbm(lbm);
+    if (st) return st;
+    if ((st = check_obs(obs, lbm))) return st;
+    const int lmax = count_lmax(lbm, obs);
+    int r = 0, n = 0;
+    if ((st = choose_route(lbm, obs, lmax, &r, &n))) return st;
+    if (max_local_points) *max_local_points = lmax;
+    if (eig_size) *eig_size = n;
+    if (route) *route = r;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
+                                const double* d_force, void* d_workspace, size_t bytes,
+                                void* stream, void** ctx_out) {
+    lbmletkf_status st = check_lbm(lbm);
+    if (st) return st;
+    if ((st = check_obs(obs, lbm))) return st;
+    if (!ctx_out) return fail(LBMLETKF_EINVAL, "ctx_out is NULL");
+    *ctx_out = nullptr;
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
+        return fail(LBMLETKF_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    const int lmax = count_lmax(lbm, obs);
+    int route = 0, n = 0;
+    if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
+    Layout L = make_layout(lbm, obs, lmax, route);
+    if (bytes < L.total) return fail(LBMLETKF_EWORKSPACE, "workspace too small");
+
+    Ctx* c = new Ctx();
+    c->lbm = *lbm;
+    c->obs = *obs;
+    c->obs.points = nullptr;
+    c->dims = {lbm->nx, lbm->ny, lbm->members};
+    c->nobs = obs->n_points * obs->nvar;
+    c->lmax = lmax;
+    c->route = route;
+    c->n_eig = n;
+    c->has_force = d_force != nullptr;
+    c->ws = reinterpret_cast<char*>(d_workspace);
+    c->L = L;
+    hipStream_t s = as_stream(stream);
+    const size_t plane = (size_t)lbm->nx * lbm->ny;
+    hipError_t e = hipSuccess;
+    if (d_force)
+        e = hipMemcpyAsync(c->ws + L.force, d_force, plane * 2 * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->pts(), obs->points, (size_t)obs->n_points * 2 * sizeof(int),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->counters(), 0, 16 * sizeof(int), s);
+    if (e == hipSuccess && lmax > 0)
+        e = launch_local_table(c->pts(), obs->n_points, obs->d_cut, lmax, lbm->nx, lbm->ny,
+                               c->loc_pt(), c->loc_g(), c->counters(), s);
+    int overflow = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&overflow, c->counters(), sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "lbmletkf_create");
+    }
+    if (overflow != 0) {
+        delete c;
+        return fail(LBMLETKF_EINVAL, "local-observation table overflow");
+    }
+    *ctx_out = c;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_destroy(void* ctx) {
+    Ctx* c = as_ctx(ctx);
+    if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
+    for (auto& r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    delete c;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const double* d_uv,
+                                          double* d_f, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_uv || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
+    hipError_t e = launch_init_equilibrium(d_rho, d_uv, d_f, c->dims, as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "init_equilibrium");
+}
+
+lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, double* d_f, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_canonical || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if ((const void*)d_canonical == (const void*)d_f)
+        return fail(LBMLETKF_EINVAL, "import cannot run in place");
+    hipError_t e = launch_import(d_canonical, d_f, c->dims, as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "import");
+}
+
+lbmletkf_status lbmletkf_export(void* ctx, const double* d_f, double* d_canonical, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_canonical || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if ((const void*)d_canonical == (const void*)d_f)
+        return fail(LBMLETKF_EINVAL, "export cannot run in place");
+    hipError_t e = launch_export(d_f, d_canonical, c->dims, as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "export");
+}
+
+lbmletkf_status lbm_ensemble_step(void* ctx, double* d_f, int32_t nsteps, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(LBMLETKF_EINVAL, "nsteps must be >= 0");
+    hipStream_t s = as_stream(stream);
+    double* a = d_f;
+    double* b = c->fbuf();
+    for (int k = 0; k < nsteps; ++k) {
+        StageTimer t(c, kStageCollide, s);
+        hipError_t e = launch_stream_collide(a, b, c->force(), c->dims, c->lbm.tau0, c->lbm.cs,
+                                             c->lbm.mu, s);
+        if (e != hipSuccess) return hip_fail(e, "stream_collide");
+        std::swap(a, b);
+    }
+    if (a != d_f) {
+        const size_t bytes = (size_t)c->dims.nx * c->dims.ny * 9 * c->dims.members * sizeof(double);
+        hipError_t e = hipMemcpyAsync(d_f, a, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "ping-pong copy");
+    }
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status observe(void* ctx, const double* d_f, double* d_yf, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_yf) return fail(LBMLETKF_EINVAL, "NULL argument");
+    StageTimer t(c, kStageObserve, as_stream(stream));
+    hipError_t e = launch_observe(d_f, c->pts(), c->obs.n_points, c->obs.nvar, d_yf, c->dims,
+                                  as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "observe");
+}
+
+lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const double* d_yo,
+                              void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_yf || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (c->dims.members < 2) return fail(LBMLETKF_EINVAL, "analysis needs >= 2 members");
+    hipStream_t s = as_stream(stream);
+    {
+        StageTimer t(c, kStageStats, s);
+        hipError_t e = launch_obs_stats(d_yf, d_yo, c->nobs, c->dims.members, c->ybar(), c->dY(),
+                                        c->dvec(), c->K(), s);
+        if (e != hipSuccess) return hip_fail(e, "obs_stats");
+    }
+    AnalysisParams p{};
+    p.f = d_f;
+    p.nx = c->dims.nx;
+    p.ny = c->dims.ny;
+    p.members = c->dims.members;
+    p.dY = c->dY();
+    p.K = c->K();
+    p.dvec = c->dvec();
+    p.loc_pt = c->loc_pt();
+    p.loc_g = c->loc_g();
+    p.lmax = c->lmax;
+    p.nvar = c->obs.nvar;
+    p.nobs = c->nobs;
+    for (int v = 0; v < 3; ++v)
+        p.rinv[v] = v < c->obs.nvar ? 1.0 / (c->obs.sigma[v] * c->obs.sigma[v]) : 0.0;
+    p.a = (c->dims.members - 1) / c->obs.beta;
+    p.sqrt_beta = std::sqrt(c->obs.beta);
+    p.eig_fail = c->counters() + 1;
+    StageTimer t(c, kStageAnalysis, s);
+    hipError_t e = launch_analysis(p, c->route, c->n_eig, s);
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "analysis");
+}
+
+lbmletkf_status lbmletkf_diagnostics(void* ctx, const double* d_f, const double* d_truth_uv,
+                                     double* d_diag, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_diag) return fail(LBMLETKF_EINVAL, "NULL argument");
+    StageTimer t(c, kStageDiag, as_stream(stream));
+    hipError_t e = launch_diag(d_f, d_truth_uv, c->dims, c->partial(), kDiagBlocks, d_diag,
+                               as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
+}
+
+lbmletkf_status run_cycle(void* ctx, double* d_f, int32_t nsteps, const double* d_yo,
+                          const double* d_truth_uv, double* d_diag, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    lbmletkf_status st = lbm_ensemble_step(ctx, d_f, nsteps, stream);
+    if (st) return st;
+    if (d_diag && (st = lbmletkf_diagnostics(ctx, d_f, d_truth_uv, d_diag, stream))) return st;
+    if ((st = observe(ctx, d_f, c->yf(), stream))) return st;
+    if ((st = letkf_analyze(ctx, d_f, c->yf(), d_yo, stream))) return st;
+    if (d_diag &&
+        (st = lbmletkf_diagnostics(ctx, d_f, d_truth_uv, d_diag + LBMLETKF_DIAG_LEN, stream)))
+        return st;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_moments(void* ctx, const double* d_f, double* d_out, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_out) return fail(LBMLETKF_EINVAL, "NULL argument");
+    hipError_t e = launch_moments(d_f, d_out, c->dims, as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "moments");
+}
+
+lbmletkf_status lbmletkf_synth_obs(const double* d_y, const double* d_eps, const double* d_sigma,
+                                   double* d_yo, int32_t n, void* stream) {
+    if (!d_y || !d_eps || !d_sigma || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (n < 0) return fail(LBMLETKF_EINVAL, "n must be >= 0");
+    if (n == 0) return LBMLETKF_OK;
+    hipError_t e = launch_synth_obs(d_y, d_eps, d_sigma, d_yo, n, as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "synth_obs");
+}
+
+lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig_size,
+                              int32_t* route) {
+    Ctx* c = as_ctx(ctx);
+    if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
+    if (max_local_points) *max_local_points = c->lmax;
+    if (eig_size) *eig_size = c->n_eig;
+    if (route) *route = c->route;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable) {
+    Ctx* c = as_ctx(ctx);
+    if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
+    c->profiling = enable != 0;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !ms || !counts) return fail(LBMLETKF_EINVAL, "NULL argument");
+    for (int k = 0; k < LBMLETKF_NSTAGES; ++k) {
+        ms[k] = 0.0;
+        counts[k] = 0;
+    }
+    lbmletkf_status st = LBMLETKF_OK;
+    for (auto& r : c->recs) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && st == LBMLETKF_OK) st = hip_fail(e, "profile_collect");
+        ms[r.stage] += t;
+        counts[r.stage] += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    c->recs.clear();
+    return st;
+}
+
+}  // extern "C"
