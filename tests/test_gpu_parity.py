@@ -295,6 +295,7 @@ def test_run_cycle_tiny_full_run():
     assert ra.mean() < rf.mean()
 
 
+@pytest.mark.timeout(400)
 def test_run_cycle_paper_scale_one_cycle():
     say("run_cycle 256x256 M=64 one cycle")
     diags, fe_gpu, ctx = _gpu_osse(PAPER, 1)
