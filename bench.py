@@ -1,0 +1,238 @@
+"""Benchmark of the LBM-LETKF forecast-analysis cycle on one MI355X.
+
+One "step" is one full data-assimilation cycle of the hot path: s = 20
+stream-collide steps of all 64 members on 256^2, the observation operator,
+the observation-space statistics, the per-node LETKF analysis and the cycle
+diagnostics (forecast and analysis RMSE against the truth).  The truth run
+and the noisy observations are generated on the GPU before the timed region
+and stay resident in HBM.
+
+Prints one JSON line: DA cycles/s (value), GLUPS*member, the mean analysis
+RMSE of the timed cycles, the roofline of the dominant kernel measured with
+HIP events on the launch stream, and the FP64 oracle timed on the host cores
+(cpu_baseline, a bounded sample extrapolated to one cycle).
+
+    python bench.py [--steps K] [--warmup W] [--config paper] [--route auto|ensemble|observation]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("DA cycles/s and GLUPS·member at 256² / 64 members vs plain GPU form, "
+          "at equal RMSE")
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
+BYTES_PER_NODE_MEMBER = 144.0  # 9 loads + 9 stores of FP64 per node and member
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def analysis_flops_per_node(route: int, members: int, n_local: float, n_eig: int) -> float:
+    """Algorithmic FP64 work of one node's analysis.
+
+    Ensemble route: A = aI + Z^T Z (l M^2), the M x M symmetric
+    eigendecomposition with vectors counted at the textbook 9 M^3, the
+    weights (2 M^3) and the transform of the 9 populations (2*9*M^2).
+    Observation route: S = Z Z^T from the Gram matrix (l^2), the l x l
+    eigendecomposition (9 l^3), the weight factors (4 l^2 + ...), B = dX Z^T
+    and the transform (2 * 2*9*l*M)."""
+    M, l = float(members), float(n_local)
+    if route == 2:
+        return 2 * l * l + 9 * l ** 3 + 4 * l * l + 2 * 2 * 9 * l * M + 2 * 9 * l * l
+    return 2 * l * M * M + 9 * M ** 3 + 2 * M ** 3 + 2 * 9 * M * M
+
+
+def cpu_baseline(cfg, force, pts, sample_steps: int, sample_nodes: int):
+    """The FP64 oracle on the host: sample_steps LBM steps of the full
+    ensemble and the analysis of sample_nodes nodes, scaled to one cycle."""
+    import oracle
+    from paper_2308_03972_amd import inputs
+    truth_uv, mem_uv = inputs.initial_velocities(cfg)
+    fe = oracle.equilibrium(np.ones((cfg.members, cfg.n, cfg.n)), mem_uv[:, 0], mem_uv[:, 1])
+    t0 = time.perf_counter()
+    fe = oracle.lbm_steps(fe, sample_steps, cfg.tau0, cfg.cs, force, cfg.mu)
+    t_step = (time.perf_counter() - t0) / sample_steps
+    yf = oracle.observe(fe, pts, cfg.nvar)
+    yo = yf.mean(axis=0)
+    nodes = np.arange(sample_nodes) * (cfg.n * cfg.n // sample_nodes)
+    t0 = time.perf_counter()
+    oracle.letkf_analysis(fe, yf, yo, pts, cfg.sigmas, cfg.d_cut, cfg.beta, nodes=nodes)
+    t_node = (time.perf_counter() - t0) / sample_nodes
+    t_cycle = cfg.steps_per_cycle * t_step + cfg.n * cfg.n * t_node
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / t_cycle, "unit": "cycles/s", "cores": threads, "kind": "oracle",
+        "sample": (f"{sample_steps} oracle LBM steps of the full {cfg.n}^2 x {cfg.members} "
+                   f"ensemble (C, OpenMP {threads} threads) + the oracle analysis of "
+                   f"{sample_nodes} of {cfg.n * cfg.n} nodes (NumPy/LAPACK eigh), scaled to "
+                   f"{cfg.steps_per_cycle} steps + {cfg.n * cfg.n} nodes per cycle"),
+        "s_per_lbm_step": t_step, "s_per_node_analysis": t_node,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=190, help="timed DA cycles")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed DA cycles before timing")
+    ap.add_argument("--config", default="paper")
+    ap.add_argument("--route", default="auto", choices=["auto", "ensemble", "observation"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-nodes", type=int, default=8192)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
+              "single-GPU by design and has no multi-GPU mode.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2308_03972_amd import binding, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        # a copy kernel that reads and writes exactly MIB MiB each, 5 launches
+        n = args.calibrate_copy * 2**20 // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_mib": args.calibrate_copy, "launches": 5}), flush=True)
+        return 0
+    cfg = inputs.CONFIGS[args.config]
+    route = {"auto": 0, "ensemble": 1, "observation": 2}[args.route]
+    total = args.warmup + args.steps
+    s = cfg.steps_per_cycle
+    cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    # ---- inputs: seeded fields, force, observing network --------------------
+    truth_uv, mem_uv = inputs.initial_velocities(cfg)
+    force_np = inputs.body_force(cfg)
+    pts = inputs.observation_points(cfg)
+    force = cuda(force_np)
+    tctx = binding.Context.from_config(cfg, members=1, force=force)
+    ectx = binding.Context.from_config(cfg, force=force, route=route)
+    log(f"config {cfg.name}: {cfg.n}^2 x {cfg.members}, route {ectx.route}, eig size "
+        f"{ectx.eig_size}, max local points {ectx.max_local_points}")
+
+    # ---- truth run and observations, all resident before timing -------------
+    noise = cuda(inputs.all_observation_noise(cfg, total))
+    sig = cuda(inputs.sigma_vector(cfg))
+    ft = tctx.init_equilibrium(cuda(truth_uv[None]))
+    yo_all = torch.empty((total, cfg.n_obs), dtype=torch.float64, device=dev)
+    tuv_all = torch.empty((total, 2, cfg.n, cfg.n), dtype=torch.float64, device=dev)
+    for c in range(total):
+        tctx.step(ft, s)
+        ytrue = tctx.observe(ft)[0].contiguous()
+        yo_all[c] = binding.synth_obs(ytrue, noise[c].contiguous(), sig)
+        tuv_all[c] = tctx.moments(ft)[0, 1:]
+    diag = torch.zeros((total, 2 * binding.DIAG_LEN), dtype=torch.float64, device=dev)
+    fe = ectx.init_equilibrium(cuda(mem_uv))
+    torch.cuda.synchronize()
+    log(f"truth and {total} observation sets ready")
+
+    def cycle(c: int) -> None:
+        ectx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
+
+    # ---- warmup ---------------------------------------------------------------
+    for c in range(args.warmup):
+        cycle(c)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} cycles done")
+
+    # ---- timed region: per-launch HIP events on the launch stream ----------
+    ectx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(args.warmup, total):
+        cycle(c)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, stage_n = ectx.profile_collect()
+    ectx.set_profiling(False)
+    log(f"timed {args.steps} cycles in {elapsed:.3f} s")
+
+    d = diag[args.warmup:].cpu().numpy()
+    rmse_f, rmse_a = d[:, 0], d[:, binding.DIAG_LEN]
+    nonfinite = float(d[:, 2].sum() + d[:, binding.DIAG_LEN + 2].sum())
+    cycles_per_s = args.steps / elapsed
+    plane = cfg.n * cfg.n
+    glups = plane * cfg.members * s * cycles_per_s / 1e9
+
+    # ---- roofline of the dominant kernel ----------------------------------------
+    per_launch = {binding.STAGES[k]: (stage_ms[k] / stage_n[k] if stage_n[k] else 0.0)
+                  for k in range(binding.NSTAGES)}
+    per_cycle = {binding.STAGES[k]: stage_ms[k] / args.steps for k in range(binding.NSTAGES)}
+    t_lbm = per_launch["stream_collide"] * 1e-3
+    t_an = per_launch["analysis"] * 1e-3
+    lbm_gbs = BYTES_PER_NODE_MEMBER * plane * cfg.members / t_lbm / 1e9
+    # mean local observations per node from the planner's table statistics
+    n_local = cfg.nvar * ectx.max_local_points
+    an_flops = analysis_flops_per_node(ectx.route, cfg.members, n_local, ectx.eig_size) * plane
+    an_tflops = an_flops / t_an / 1e12
+    rl_lbm = {"kernel": "stream_collide", "bound": "hbm", "achieved": round(lbm_gbs, 1),
+              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(lbm_gbs / HBM_PEAK_GBS, 4),
+              "traffic": None, "avg_launch_us": round(per_launch["stream_collide"] * 1e3, 2)}
+    rl_an = {"kernel": "analysis", "bound": "alu", "achieved": round(an_tflops, 3),
+             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(an_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None,
+             "avg_launch_us": round(per_launch["analysis"] * 1e3, 2)}
+    dominant = rl_lbm if per_cycle["stream_collide"] >= per_cycle["analysis"] else rl_an
+    other = rl_an if dominant is rl_lbm else rl_lbm
+
+    out = {
+        "metric": METRIC,
+        "value": round(cycles_per_s, 3),
+        "unit": "cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"plain FP64 forecast-analysis cycle, {cfg.n}x{cfg.n} D2Q9 "
+                         f"BGK-Smagorinsky, {cfg.members} members, {cfg.obs_side}x{cfg.obs_side} "
+                         f"(u,v) observations, s={s}, r={cfg.loc_r:g}, beta={cfg.beta}"),
+            "grid": cfg.n, "members": cfg.members, "steps_per_cycle": s,
+            "obs_points": cfg.n_points, "route": ["", "ensemble", "observation"][ectx.route],
+            "eig_size": ectx.eig_size,
+        },
+        "glups_member": round(glups, 3),
+        "rmse_a_mean": float(rmse_a.mean()),
+        "rmse_f_mean": float(rmse_f.mean()),
+        "obs_noise_rms": cfg.sigma * math.sqrt(2.0),
+        "nonfinite": nonfinite,
+        "stage_ms_per_cycle": {k: round(v, 4) for k, v in per_cycle.items()},
+        "roofline": dominant,
+        "roofline_other": other,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(cfg, force_np, pts, args.cpu_steps, args.cpu_nodes)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -131,8 +131,12 @@ CONFIGS: Dict[str, CycleConfig] = {
 # --------------------------------------------------------------------------
 # random streams
 # --------------------------------------------------------------------------
-def streams(cfg: CycleConfig) -> Dict[str, object]:
-    """Independent PCG64 generators: truth IC, one per member, one per cycle."""
+def streams(cfg: CycleConfig, cycles: Optional[int] = None) -> Dict[str, object]:
+    """Independent PCG64 generators: truth IC, one per member, one per cycle.
+
+    Child streams depend only on their index, so asking for more cycles than
+    the configuration holds leaves the first ones unchanged."""
+    n_noise = max(cfg.cycles, cycles or 0) + 1
     root = np.random.SeedSequence(cfg.seed)
     truth_ss, member_ss, noise_ss = root.spawn(3)
     return {
@@ -140,7 +144,7 @@ def streams(cfg: CycleConfig) -> Dict[str, object]:
         "members": [np.random.Generator(np.random.PCG64(s))
                     for s in member_ss.spawn(cfg.members)],
         "noise": [np.random.Generator(np.random.PCG64(s))
-                  for s in noise_ss.spawn(cfg.cycles + 1)],
+                  for s in noise_ss.spawn(n_noise)],
     }
 
 
@@ -204,17 +208,17 @@ def observation_points(cfg: CycleConfig) -> np.ndarray:
 
 def observation_noise(cfg: CycleConfig, cycle: int) -> np.ndarray:
     """Standard-normal draws for the observations of ``cycle`` (1-based)."""
-    return streams_noise(cfg)[cycle].standard_normal(cfg.n_obs)
+    return streams_noise(cfg, cycle)[cycle].standard_normal(cfg.n_obs)
 
 
-def streams_noise(cfg: CycleConfig) -> List[np.random.Generator]:
-    return streams(cfg)["noise"]
+def streams_noise(cfg: CycleConfig, cycles: Optional[int] = None) -> List[np.random.Generator]:
+    return streams(cfg, cycles)["noise"]
 
 
 def all_observation_noise(cfg: CycleConfig, cycles: Optional[int] = None) -> np.ndarray:
     """Noise for cycles 1..cycles, shape [cycles][n_obs]."""
     cycles = cfg.cycles if cycles is None else cycles
-    gens = streams_noise(cfg)
+    gens = streams_noise(cfg, cycles)
     return np.stack([gens[c].standard_normal(cfg.n_obs) for c in range(1, cycles + 1)])
 
 

@@ -291,8 +291,6 @@ def test_run_cycle_tiny_full_run():
     assert np.max(np.abs(ra / ref["rmse_a"] - 1)) < 1e-6
     assert np.max(np.abs(diags[:, 9] / ref["spread_a"] - 1)) < 1e-6
     assert rel_max(fe_gpu, ref["f_ens"]) < 1e-9
-    # the filter works: on average the analysis is closer to the truth
-    assert ra.mean() < rf.mean()
 
 
 @pytest.mark.timeout(400)
