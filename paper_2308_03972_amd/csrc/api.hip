@@ -13,7 +13,8 @@
 using namespace lbmletkf;
 
 namespace lbmletkf {
-int analysis_lds_bytes(int n, int nz);
+int analysis_lds_bytes(int n, int nz, int route);
+int diag_blocks_for(int plane);
 }
 
 namespace {
@@ -31,7 +32,6 @@ lbmletkf_status hip_fail(hipError_t e, const char* where) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kDiagBlocks = 512;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -173,7 +173,7 @@ lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_pa
     if (sz == 0)
         return fail(LBMLETKF_EUNSUPPORTED,
                     "observation route needs at most 64 local observations per node");
-    if (analysis_lds_bytes(sz, nz) > 65536)
+    if (analysis_lds_bytes(sz, nz, r) > 160 * 1024)
         return fail(LBMLETKF_EUNSUPPORTED, "too many local observations for the LDS budget");
     *route = r;
     *n = sz;
@@ -201,7 +201,7 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
     L.dvec = take(nobs * sizeof(double));
     L.K = take(route == 2 ? nobs * nobs * sizeof(double) : 0);
     L.yf = take(nobs * p->members * sizeof(double));
-    L.partial = take((size_t)kDiagBlocks * 8 * sizeof(double));
+    L.partial = take((size_t)diag_blocks_for((int)plane) * 8 * sizeof(double));
     L.counters = take(16 * sizeof(int));
     L.total = off;
     return L;
@@ -423,7 +423,8 @@ lbmletkf_status lbmletkf_diagnostics(void* ctx, const double* d_f, const double*
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_diag) return fail(LBMLETKF_EINVAL, "NULL argument");
     StageTimer t(c, kStageDiag, as_stream(stream));
-    hipError_t e = launch_diag(d_f, d_truth_uv, c->dims, c->partial(), kDiagBlocks, d_diag,
+    hipError_t e = launch_diag(d_f, d_truth_uv, c->dims, c->partial(),
+                               diag_blocks_for(c->dims.nx * c->dims.ny), d_diag,
                                as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
 }

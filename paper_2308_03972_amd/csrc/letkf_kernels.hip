@@ -87,17 +87,20 @@ __global__ void observe_kernel(const double* __restrict__ f, const int* __restri
 // ---------------------------------------------------------------------------
 // observation-space statistics: y_bar, dY[q][m], d = y^o - y_bar
 // ---------------------------------------------------------------------------
-__global__ void obs_stats_kernel(const double* __restrict__ yf, const double* __restrict__ yo,
-                                 int nobs, int members, double* __restrict__ ybar,
-                                 double* __restrict__ dY, double* __restrict__ dvec) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void obs_stats_kernel(
+    const double* __restrict__ yf, const double* __restrict__ yo, int nobs, int members,
+    double* __restrict__ ybar, double* __restrict__ dY, double* __restrict__ dvec) {
+    // one wavefront per observation q, lane = member
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int m = threadIdx.x & 63;
     if (q >= nobs) return;
-    double s = 0.0;
-    for (int m = 0; m < members; ++m) s += yf[(size_t)m * nobs + q];
-    const double mean = s / members;
-    for (int m = 0; m < members; ++m) dY[(size_t)q * members + m] = yf[(size_t)m * nobs + q] - mean;
-    ybar[q] = mean;
-    dvec[q] = yo[q] - mean;
+    const double v = m < members ? yf[(size_t)m * nobs + q] : 0.0;
+    const double mean = wave_sum(v) / members;
+    if (m < members) dY[(size_t)q * members + m] = v - mean;
+    if (m == 0) {
+        ybar[q] = mean;
+        dvec[q] = yo[q] - mean;
+    }
 }
 
 // K = dY dY^T (unweighted observation-space Gram matrix)
@@ -152,8 +155,14 @@ __global__ void local_table_kernel(const int* __restrict__ pts, int npts, double
 }
 
 // ---------------------------------------------------------------------------
-// wave-level parallel Jacobi on an N x N symmetric matrix (N even, N <= 64)
-// lane i < N holds row i of S and of U (U accumulates the rotations).
+// wave-level parallel Jacobi on SEGS independent N x N symmetric matrices
+// (N even).  Lane l belongs to segment seg = l / N and holds row i = l % N of
+// its matrix S and of the accumulated rotation matrix U in registers.
+// Round P rotates the pairs (2k+P, 2k+P+1) and swaps them (Brent-Luk
+// ordering): rows are published to LDS, both lanes of a pair read a_pp,
+// a_qq, a_pq from there (so they derive bit-identical rotations), the row
+// mix reads the partner's pre-round row from LDS, and the column mix of S
+// and U is in-register with the pair's (c, s) read back from LDS.
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ double extract_lane_entry(const double (&R)[N], int col) {
@@ -163,141 +172,348 @@ __device__ __forceinline__ double extract_lane_entry(const double (&R)[N], int c
     return v;
 }
 
-template <int N, int P>
-__device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], double* cs,
-                                             int lane) {
-    const bool first = ((lane - P) & 1) == 0;
-    int partner = first ? lane + 1 : lane - 1;
-    const bool paired = lane < N && partner >= 0 && partner < N;
-    if (!paired) partner = lane;
-    const double d_own = extract_lane_entry<N>(S, lane);
-    const double e_own = extract_lane_entry<N>(S, partner);
-    const double d_par = __shfl(d_own, partner, kWave);
-    const double apq = __shfl(e_own, first ? lane : partner, kWave);  // from the first lane
-    const double app = first ? d_own : d_par;
-    const double aqq = first ? d_par : d_own;
-    double c = 1.0, s = 0.0;
-    if (paired && apq != 0.0) {
-        const double theta = (aqq - app) / (2.0 * apq);
-        double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-        if (theta < 0.0) t = -t;
-        c = 1.0 / sqrt(1.0 + t * t);
-        s = t * c;
+template <int N, int SEGS, int P>
+__device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], double* rows,
+                                             double2* cs, int lane) {
+    constexpr int RS = N;  // row stride (doubles)
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    double* segrows = rows + (size_t)sbase * RS;
+    // publish this lane's row
+    wave_lds_sync();
+    if (active) {
+        double2* my = reinterpret_cast<double2*>(segrows + (size_t)i * RS);
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) my[k] = make_double2(S[2 * k], S[2 * k + 1]);
     }
-    // publish (c, s); the pair (r, r+1) is read from its first lane r
     wave_lds_sync();
-    cs[2 * lane] = c;
-    cs[2 * lane + 1] = s;
+    const bool first = ((i - P) & 1) == 0;
+    const int pi = first ? i + 1 : i - 1;
+    const bool paired = active && pi >= 0 && pi < N;
+    const int p = first ? i : pi;
+    double c = 1.0, s = 0.0;
+    if (paired) {
+        const double app = segrows[(size_t)p * RS + p];
+        const double aqq = segrows[(size_t)(p + 1) * RS + p + 1];
+        const double apq = segrows[(size_t)p * RS + p + 1];
+        if (apq != 0.0) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+            if (theta < 0.0) t = -t;
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+        }
+    }
+    cs[lane] = make_double2(c, s);
+    // rows: S <- P^T J^T S, from the partner's row as published
+    if (paired) {
+        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)pi * RS);
+        const double sg = first ? s : -s;
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) {
+            const double2 v = pr[k];
+            S[2 * k] = c * v.x + sg * S[2 * k];
+            S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
+        }
+    }
     wave_lds_sync();
-    // columns: S <- S J P and U <- U J P (rotate, then swap the pair)
+    // columns: S <- S J P, U <- U J P, pair (r, r+1) rotated by its first lane's (c, s)
 #pragma unroll
     for (int r = P; r + 1 < N; r += 2) {
-        const double cr = cs[2 * r], sr = cs[2 * r + 1];
+        const double2 q = cs[sbase + r];
         const double a0 = S[r], a1 = S[r + 1];
-        S[r] = sr * a0 + cr * a1;
-        S[r + 1] = cr * a0 - sr * a1;
+        S[r] = q.y * a0 + q.x * a1;
+        S[r + 1] = q.x * a0 - q.y * a1;
         const double u0 = U[r], u1 = U[r + 1];
-        U[r] = sr * u0 + cr * u1;
-        U[r + 1] = cr * u0 - sr * u1;
-    }
-    // rows: S <- P^T J^T S (rows of the pair exchanged across lanes)
-    const double sg = first ? s : -s;
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-        const double par = __shfl(S[r], partner, kWave);
-        S[r] = c * par + sg * S[r];
+        U[r] = q.y * u0 + q.x * u1;
+        U[r + 1] = q.x * u0 - q.y * u1;
     }
 }
 
-// Returns the number of sweeps used (max_sweeps + 1 if not converged).
-template <int N>
-__device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* cs, int lane,
-                          int max_sweeps) {
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+// Sweeps until every segment's off-diagonal Frobenius norm is below 1e-13
+// of its diagonal norm.  Returns the sweeps used, max_sweeps + 1 if a segment
+// did not converge.  `red` holds 2 doubles per lane.
+template <int N, int SEGS>
+__device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2* cs,
+                          double* red, int lane, int max_sweeps) {
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    for (int sweep = 0;; ++sweep) {
         double off = 0.0, dg = 0.0;
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             const double v2 = S[r] * S[r];
-            if (r == lane) dg += v2; else off += v2;
+            if (r == i) dg += v2; else off += v2;
         }
-        if (lane >= N) { off = 0.0; dg = 0.0; }
-        off = wave_sum(off);
-        dg = wave_sum(dg);
-        if (off <= 1e-26 * dg) return sweep;
+        wave_lds_sync();
+        red[2 * lane] = active ? off : 0.0;
+        red[2 * lane + 1] = active ? dg : 0.0;
+        wave_lds_sync();
+        double so = 0.0, sd = 0.0;
+        for (int k = 0; k < N; ++k) {
+            so += red[2 * (sbase + k)];
+            sd += red[2 * (sbase + k) + 1];
+        }
+        const bool done = !active || so <= 1e-26 * sd;
+        if (__all(done)) return sweep;
+        if (sweep >= max_sweeps) return max_sweeps + 1;
         for (int rr = 0; rr < N / 2; ++rr) {
-            jacobi_round<N, 0>(S, U, cs, lane);
-            jacobi_round<N, 1>(S, U, cs, lane);
+            jacobi_round<N, SEGS, 0>(S, U, rows, cs, lane);
+            jacobi_round<N, SEGS, 1>(S, U, rows, cs, lane);
         }
     }
-    double off = 0.0, dg = 0.0;
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-        const double v2 = S[r] * S[r];
-        if (r == lane) dg += v2; else off += v2;
-    }
-    if (lane >= N) { off = 0.0; dg = 0.0; }
-    off = wave_sum(off);
-    dg = wave_sum(dg);
-    return off <= 1e-26 * dg ? max_sweeps : max_sweeps + 1;
+}
+
+// Block b runs on XCD b % 8; give each XCD a contiguous range of work items
+// so that nodes sharing cache lines meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int per = nblocks / 8;
+    if (b >= per * 8) return b;
+    return (b % 8) * per + b / 8;
 }
 
 // ---------------------------------------------------------------------------
-// per-node LETKF analysis; OBS selects the observation route
+// observation route: SEGS = 64 / N nodes per wavefront, eigenproblem Z Z^T
 // ---------------------------------------------------------------------------
-struct WaveLds {
-    double* dx;    // [9][64]  forecast perturbations dX (zero for lanes >= M)
-    double* u;     // [N][N+1] eigenvectors, row k = U[k][:]
-    double* cs;    // [128]    rotation parameters
-    double* psi;   // [64]
-    double* phi;   // [64]
-    double* rhs;   // [64]     route E: Z^T d~
-    double* e;     // [9][N]
-    double* b;     // [9][N]   route O: B = dX Z^T, then C = B U phi U^T
-    double* zr;    // [64]     route E: one row of Z
-    double* sw;    // [nzp]    sqrt(r_q)
-    double* dt;    // [nzp]    d~
-    int* q;        // [nzp]    observation index
+template <int N>
+struct ObsLayout {
+    static constexpr int SEGS = 64 / N;
+    // Jacobi rows, then U, then C; also stages one node's dX (9 x 64)
+    static constexpr int kRows = (SEGS * N * N > 9 * 64 ? SEGS * N * N : 9 * 64) > SEGS * 9 * N
+                                     ? (SEGS * N * N > 9 * 64 ? SEGS * N * N : 9 * 64)
+                                     : SEGS * 9 * N;
+    static constexpr int kB = SEGS * 9 * N;            // B = dX Z^T
+    static constexpr int kE = SEGS * 9 * N;            // E' = phi o (B U)
+    static constexpr int kVec = 4 * 64;                // cs/red during Jacobi; psi, pt, h after
+    static constexpr int kObs = 3 * SEGS * N;          // sw, dt, q
+    static constexpr int kXbar = SEGS * 9 + 1;
+    static constexpr int total = kRows + kB + kE + kVec + kObs + kXbar;
 };
 
-__host__ __device__ inline int lds_doubles_per_wave(int n, int nz) {
-    const int nzp = (nz + 1) & ~1;
-    return 9 * 64 + n * (n + 1) + 128 + 3 * 64 + 2 * 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
-}
-
-__device__ inline WaveLds carve(double* base, int n, int nz) {
-    const int nzp = (nz + 1) & ~1;
-    WaveLds w;
-    w.dx = base;
-    w.u = w.dx + 9 * 64;
-    w.cs = w.u + n * (n + 1);
-    w.psi = w.cs + 128;
-    w.phi = w.psi + 64;
-    w.rhs = w.phi + 64;
-    w.e = w.rhs + 64;
-    w.b = w.e + 9 * n;
-    w.zr = w.b + 9 * n;
-    w.sw = w.zr + 64;
-    w.dt = w.sw + nzp;
-    w.q = reinterpret_cast<int*>(w.dt + nzp);
-    return w;
-}
-
-template <int N, bool OBS>
-__global__ __launch_bounds__(64) void analysis_kernel(AnalysisParams p, int lds_per_wave,
-                                                      int max_sweeps) {
+template <int N>
+__global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, int max_sweeps) {
+    using L = ObsLayout<N>;
+    constexpr int SEGS = L::SEGS;
     extern __shared__ double lds[];
+    double* rows = lds;                              // [SEGS][N][N]
+    double* Bm = rows + L::kRows;                    // [SEGS][9][N]
+    double* Em = Bm + L::kB;                         // [SEGS][9][N]
+    double* vec = Em + L::kE;                        // [4][64]
+    double* sw = vec + L::kVec;                      // [SEGS][N]
+    double* dt = sw + SEGS * N;                      // [SEGS][N]
+    int* qx = reinterpret_cast<int*>(dt + SEGS * N); // [SEGS][N]
+    double* xb = reinterpret_cast<double*>(qx) + SEGS * N;  // [SEGS][9]
+    double2* cs = reinterpret_cast<double2*>(vec);   // Jacobi only
+    double* red = vec + 128;                         // Jacobi only
+
     const int lane = threadIdx.x;
-    const int node = blockIdx.x;
     const int nx = p.nx, ny = p.ny, M = p.members;
     const int plane = nx * ny;
+    const int nz = p.nvar * p.lmax;
+    const int node0 = xcd_remap(blockIdx.x, gridDim.x) * SEGS;
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    const bool mem = lane < M;
+
+    // ---- phase A (one node at a time, lane = member): x_bar, dX, local
+    //      observations and B = dX Z^T (rows of Z: sqrt(r_j) dY[q_j][:])
+    for (int sg = 0; sg < SEGS; ++sg) {
+        const int node = node0 + sg;
+        const bool valid = node < plane;
+        const int x = valid ? node % nx : 0, y = valid ? node / nx : 0;
+        double dx[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
+            dx[a] = (valid && mem) ? p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs]
+                                   : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const double xbar = wave_sum(dx[a]) / M;
+            dx[a] = mem ? dx[a] - xbar : 0.0;
+            if (lane == 0) xb[sg * 9 + a] = xbar;
+        }
+        if (lane < N) {
+            int q = 0;
+            double w = 0.0, d = 0.0;
+            if (valid && lane < nz) {
+                const int slot = lane / p.nvar, var = lane - slot * p.nvar;
+                const int k = p.loc_pt[(size_t)node * p.lmax + slot];
+                if (k >= 0) {
+                    q = k * p.nvar + var;
+                    w = sqrt(p.loc_g[(size_t)node * p.lmax + slot] * p.rinv[var]);
+                    d = w * p.dvec[q];
+                }
+            }
+            qx[sg * N + lane] = q;
+            sw[sg * N + lane] = w;
+            dt[sg * N + lane] = d;
+        }
+        // stage dX of this node in the (not yet used) Jacobi rows area
+        wave_lds_sync();
+#pragma unroll
+        for (int a = 0; a < 9; ++a) rows[a * 64 + lane] = dx[a];
+        wave_lds_sync();
+        if (lane < N) {
+            double b[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) b[a] = 0.0;
+            const double wj = sw[sg * N + lane];
+            if (wj != 0.0) {
+                const double* yrow = p.dY + (size_t)qx[sg * N + lane] * M;
+                for (int m = 0; m < M; ++m) {
+                    const double yv = yrow[m];
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) b[a] += rows[a * 64 + m] * yv;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) Bm[(sg * 9 + a) * N + lane] = b[a] * wj;
+        }
+    }
+    wave_lds_sync();
+
+    // ---- phase B: S = Z Z^T = diag(sw) K diag(sw) on the local observations
+    double S[N], U[N];
+    {
+        const double wi = active ? sw[sbase + i] : 0.0;
+        const double* Krow = p.K + (size_t)(active ? qx[sbase + i] : 0) * p.nobs;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double wk = sw[sbase + k];
+            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * Krow[qx[sbase + k]] : 0.0;
+            U[k] = (k == i && active) ? 1.0 : 0.0;
+        }
+    }
+
+    // ---- phase C: eigendecomposition
+    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, max_sweeps);
+    if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
+
+    // ---- phase D: eigenvalue functions, U to LDS, t = U^T d~, h = U psi t
+    const double lam = extract_lane_entry<N>(S, i);
+    const double sq = sqrt(1.0 + lam / p.a);
+    const double psi = 1.0 / (p.a + lam);
+    const double phi = -p.sqrt_beta / (p.a * sq * (1.0 + sq));
+    double* pt = vec;          // psi_c t_c
+    double* hv = vec + 64;     // h_j
+    wave_lds_sync();
+    if (active) {
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)(sbase + i) * N);
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
+    }
+    wave_lds_sync();
+    {
+        double t = 0.0;
+        if (active)
+            for (int k = 0; k < N; ++k) t += rows[(size_t)(sbase + k) * N + i] * dt[sbase + k];
+        pt[lane] = active ? psi * t : 0.0;
+    }
+    wave_lds_sync();
+    {
+        double h = 0.0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) h += U[c] * pt[sbase + c];
+        hv[lane] = active ? h : 0.0;
+    }
+    // ---- phase E: E' = phi o (B U)
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            double e = 0.0;
+            for (int k = 0; k < N; ++k)
+                e += Bm[(seg * 9 + a) * N + k] * rows[(size_t)(sbase + k) * N + i];
+            Em[(seg * 9 + a) * N + i] = phi * e;
+        }
+    }
+    wave_lds_sync();
+    // ---- phase F: C = E' U^T (own row of U), into the rows area
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            double cj = 0.0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) cj += Em[(seg * 9 + a) * N + c] * U[c];
+            rows[(seg * 9 + a) * N + i] = cj;
+        }
+    }
+    wave_lds_sync();
+
+    // ---- phase G (one node at a time, lane = member): apply and store
+    for (int sg = 0; sg < SEGS; ++sg) {
+        const int node = node0 + sg;
+        if (node >= plane) break;
+        const int x = node % nx, y = node / nx;
+        double dm[9], acc[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            dm[a] = 0.0;
+            acc[a] = 0.0;
+        }
+        for (int j = 0; j < N; ++j) {
+            const double wj = sw[sg * N + j];
+            const double hj = hv[sg * N + j];
+            const double z = (mem && wj != 0.0) ? wj * p.dY[(size_t)qx[sg * N + j] * M + lane] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                dm[a] += Bm[(sg * 9 + a) * N + j] * hj;
+                acc[a] += rows[(sg * 9 + a) * N + j] * z;
+            }
+        }
+        if (mem) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
+                double* slot = p.f + ((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs;
+                const double fa = *slot;
+                const double xbar = xb[sg * 9 + a];
+                *slot = xbar + p.sqrt_beta * (fa - xbar) + dm[a] + acc[a];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ensemble route: one node per wavefront, eigenproblem (M-1)/beta I + Z^T Z
+// (lane = member; sizes above M are padded with isolated (M-1)/beta rows)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int ens_lds_doubles(int n, int nz) {
+    const int nzp = (nz + 1) & ~1;
+    return 9 * 64 + n * n + 4 * 64 + 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int max_sweeps) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int nx = p.nx, ny = p.ny, M = p.members;
+    const int plane = nx * ny;
+    const int node = xcd_remap(blockIdx.x, gridDim.x);
     if (node >= plane) return;
     const int nz = p.nvar * p.lmax;
-    WaveLds w = carve(lds, N, nz);
+    const int nzp = (nz + 1) & ~1;
+    double* sdx = lds;                   // [9][64]
+    double* rows = sdx + 9 * 64;         // [N][N]  Jacobi rows, then U
+    double* vec = rows + N * N;          // [4][64]
+    double* se = vec + 4 * 64;           // [9][N]
+    double* zr = se + 9 * N;             // [64]
+    double* sw = zr + 64;                // [nz]
+    double* dt = sw + nzp;               // [nz]
+    int* qx = reinterpret_cast<int*>(dt + nzp);
+    double2* cs = reinterpret_cast<double2*>(vec);
+    double* red = vec + 128;
     const int x = node % nx, y = node / nx;
     const bool mem = lane < M;
 
-    // ---- forecast ensemble at this node: canonical f_a from its storage slot
-    double fv[9], xbar[9], dx[9];
+    double fv[9], xbar[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
@@ -306,170 +522,77 @@ __global__ __launch_bounds__(64) void analysis_kernel(AnalysisParams p, int lds_
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         xbar[a] = wave_sum(fv[a]) / M;
-        dx[a] = mem ? fv[a] - xbar[a] : 0.0;
-        w.dx[a * 64 + lane] = dx[a];
+        sdx[a * 64 + lane] = mem ? fv[a] - xbar[a] : 0.0;
     }
-
-    // ---- local observations, weights sqrt(g / sigma^2), scaled innovation
     for (int j = lane; j < nz; j += kWave) {
         const int slot = j / p.nvar, var = j - slot * p.nvar;
         const int k = p.loc_pt[(size_t)node * p.lmax + slot];
-        const double g = p.loc_g[(size_t)node * p.lmax + slot];
         const int q = k >= 0 ? k * p.nvar + var : 0;
-        const double sw = k >= 0 ? sqrt(g * p.rinv[var]) : 0.0;
-        w.q[j] = q;
-        w.sw[j] = sw;
-        w.dt[j] = sw * p.dvec[q];
+        const double w = k >= 0 ? sqrt(p.loc_g[(size_t)node * p.lmax + slot] * p.rinv[var]) : 0.0;
+        qx[j] = q;
+        sw[j] = w;
+        dt[j] = w * p.dvec[q];
     }
     wave_lds_sync();
-
-    // ---- the symmetric eigenproblem
+    // A = a I + Z^T Z and g = Z^T d~
     double S[N], U[N];
-    if constexpr (OBS) {
-        const bool row = lane < nz;
-        const double swj = row ? w.sw[lane] : 0.0;
-        const double* Krow = p.K + (size_t)(row ? w.q[lane] : 0) * p.nobs;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double v = 0.0;
-            if (row && k < nz) v = swj * w.sw[k] * Krow[w.q[k]];
-            S[k] = v;
-            U[k] = (k == lane) ? 1.0 : 0.0;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            S[k] = (k == lane) ? p.a : 0.0;
-            U[k] = (k == lane) ? 1.0 : 0.0;
-        }
-        double g = 0.0;
-        for (int j = 0; j < nz; ++j) {
-            const double z = mem ? w.sw[j] * p.dY[(size_t)w.q[j] * M + lane] : 0.0;
-            g += z * w.dt[j];
-            wave_lds_sync();
-            w.zr[lane] = z;
-            wave_lds_sync();
-#pragma unroll
-            for (int k = 0; k < N; ++k) S[k] += z * w.zr[k];
-        }
-        w.rhs[lane] = g;
+    for (int k = 0; k < N; ++k) {
+        S[k] = (k == lane) ? p.a : 0.0;
+        U[k] = (k == lane) ? 1.0 : 0.0;
     }
-    const int sweeps = jacobi_eig<N>(S, U, w.cs, lane, max_sweeps);
+    double g = 0.0;
+    for (int j = 0; j < nz; ++j) {
+        const double z = mem ? sw[j] * p.dY[(size_t)qx[j] * M + lane] : 0.0;
+        g += z * dt[j];
+        wave_lds_sync();
+        zr[lane] = z;
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < N; ++k) S[k] += z * zr[k];
+    }
+    const int sweeps = jacobi_eig<N, 1>(S, U, rows, cs, red, lane, max_sweeps);
     if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
-
-    // ---- eigenvalue functions and U in LDS
     const double lam = extract_lane_entry<N>(S, lane);
-    double psi, phi;
-    if constexpr (OBS) {
-        const double s = sqrt(1.0 + lam / p.a);
-        psi = 1.0 / (p.a + lam);
-        phi = -p.sqrt_beta / (p.a * s * (1.0 + s));
-    } else {
-        psi = 1.0 / lam;
-        phi = sqrt((M - 1) / lam);
-    }
+    const double psi = lane < N ? 1.0 / lam : 0.0;
+    const double mu = lane < N ? sqrt((M - 1) / lam) : 0.0;
+    double* gv = vec;        // g
+    wave_lds_sync();
+    gv[lane] = g;
     if (lane < N) {
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)lane * N);
 #pragma unroll
-        for (int c = 0; c < N; ++c) w.u[lane * (N + 1) + c] = U[c];
+        for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
     }
     wave_lds_sync();
-    // t_c = sum_k U[k][c] rhs_k
-    double tc = 0.0;
+    double t = 0.0;
+    double e[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) e[a] = 0.0;
     if (lane < N) {
         for (int k = 0; k < N; ++k) {
-            const double r = OBS ? (k < nz ? w.dt[k] : 0.0) : w.rhs[k];
-            tc += w.u[k * (N + 1) + lane] * r;
+            const double ukc = rows[(size_t)k * N + lane];
+            t += ukc * gv[k];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) e[a] += sdx[a * 64 + k] * ukc;
         }
     }
-    double e[9];
-    if constexpr (OBS) {
-        // B[a][j] = sqrt(r_j) sum_m dX[a][m] dY[q_j][m]
-        double bj[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) bj[a] = 0.0;
-        if (lane < nz) {
-            const double* row = p.dY + (size_t)w.q[lane] * M;
-            for (int m = 0; m < M; ++m) {
-                const double yv = row[m];
-#pragma unroll
-                for (int a = 0; a < 9; ++a) bj[a] += w.dx[a * 64 + m] * yv;
-            }
-            const double swj = w.sw[lane];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) bj[a] *= swj;
-        }
-        if (lane < N) {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) w.b[a * N + lane] = bj[a];
-        }
-        wave_lds_sync();
-        // E = B U
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double acc = 0.0;
-            if (lane < N)
-                for (int k = 0; k < N; ++k) acc += w.b[a * N + k] * w.u[k * (N + 1) + lane];
-            e[a] = acc;
-        }
-    } else {
-        // E = dX U
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double acc = 0.0;
-            if (lane < N)
-                for (int k = 0; k < N; ++k) acc += w.dx[a * 64 + k] * w.u[k * (N + 1) + lane];
-            e[a] = acc;
-        }
-    }
-    // mean increment dX w_bar = sum_c E[a][c] psi_c t_c
     double dmean[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) dmean[a] = wave_sum(lane < N ? e[a] * psi * tc : 0.0);
+    for (int a = 0; a < 9; ++a) dmean[a] = wave_sum(lane < N ? e[a] * psi * t : 0.0);
     if (lane < N) {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) w.e[a * N + lane] = e[a] * phi;
+        for (int a = 0; a < 9; ++a) se[a * N + lane] = e[a] * mu;
     }
     wave_lds_sync();
-
-    double xa[9];
-    if constexpr (OBS) {
-        // C[a][j] = sum_c E'[a][c] U[j][c]  (lane j, own row of U)
-        if (lane < N) {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                double acc = 0.0;
-#pragma unroll
-                for (int c = 0; c < N; ++c) acc += w.e[a * N + c] * U[c];
-                w.b[a * N + lane] = acc;
-            }
-        }
-        wave_lds_sync();
-        double acc[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) acc[a] = 0.0;
-        if (mem) {
-            for (int j = 0; j < nz; ++j) {
-                const double z = w.sw[j] * p.dY[(size_t)w.q[j] * M + lane];
-#pragma unroll
-                for (int a = 0; a < 9; ++a) acc[a] += w.b[a * N + j] * z;
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) xa[a] = xbar[a] + p.sqrt_beta * dx[a] + dmean[a] + acc[a];
-    } else {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double acc = 0.0;
-#pragma unroll
-            for (int c = 0; c < N; ++c) acc += w.e[a * N + c] * U[c];
-            xa[a] = xbar[a] + dmean[a] + acc;
-        }
-    }
     if (mem) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc += se[a * N + c] * U[c];
             const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs] = xa[a];
+            p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs] = xbar[a] + dmean[a] + acc;
         }
     }
 }
@@ -479,17 +602,20 @@ __global__ __launch_bounds__(64) void analysis_kernel(AnalysisParams p, int lds_
 // density range.  Deterministic two-pass reduction.
 // ---------------------------------------------------------------------------
 constexpr int kDiagBlock = 256;
+constexpr int kDiagNodes = 64;  // nodes per block; 4 member groups per node
 constexpr int kDiagFields = 5;  // err2, spread2, nonfinite, rho_min, rho_max
 
 __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
     const double* __restrict__ f, const double* __restrict__ truth_uv, int nx, int ny,
     int members, double* __restrict__ partial) {
     const int plane = nx * ny;
-    double err2 = 0.0, spr2 = 0.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
-    for (int i = blockIdx.x * kDiagBlock + threadIdx.x; i < plane; i += gridDim.x * kDiagBlock) {
+    const int tx = threadIdx.x & (kDiagNodes - 1);
+    const int g = threadIdx.x / kDiagNodes;  // member group 0..3
+    const int i = blockIdx.x * kDiagNodes + tx;
+    double su = 0.0, sv = 0.0, suu = 0.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
+    if (i < plane) {
         const int y = i / nx, x = i - y * nx;
-        double su = 0.0, sv = 0.0, suu = 0.0;
-        for (int m = 0; m < members; ++m) {
+        for (int m = g; m < members; m += 4) {
             double rho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
@@ -507,14 +633,72 @@ __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
             sv += v;
             suu += u * u + v * v;
         }
-        const double ub = su / members, vb = sv / members;
-        if (truth_uv) {
-            const double du = ub - truth_uv[i], dv = vb - truth_uv[plane + i];
-            err2 += du * du + dv * dv;
-        }
-        if (members > 1) spr2 += (suu - members * (ub * ub + vb * vb)) / (members - 1);
     }
+    __shared__ double part[6][kDiagBlock];
+    part[0][threadIdx.x] = su;
+    part[1][threadIdx.x] = sv;
+    part[2][threadIdx.x] = suu;
+    part[3][threadIdx.x] = bad;
+    part[4][threadIdx.x] = rmin;
+    part[5][threadIdx.x] = rmax;
+    __syncthreads();
+    // combine the 4 member groups of each node (fixed order), then the nodes
+    __shared__ double red[kDiagFields][kDiagNodes];
+    if (threadIdx.x < kDiagNodes) {
+        double u = 0.0, v = 0.0, uu = 0.0, b = 0.0, lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < 4; ++k) {
+            const int t = k * kDiagNodes + tx;
+            u += part[0][t];
+            v += part[1][t];
+            uu += part[2][t];
+            b += part[3][t];
+            lo = fmin(lo, part[4][t]);
+            hi = fmax(hi, part[5][t]);
+        }
+        double err2 = 0.0, spr2 = 0.0;
+        if (i < plane) {
+            const double ub = u / members, vb = v / members;
+            if (truth_uv) {
+                const double du = ub - truth_uv[i], dv = vb - truth_uv[plane + i];
+                err2 = du * du + dv * dv;
+            }
+            if (members > 1) spr2 = (uu - members * (ub * ub + vb * vb)) / (members - 1);
+        }
+        red[0][tx] = err2;
+        red[1][tx] = spr2;
+        red[2][tx] = b;
+        red[3][tx] = lo;
+        red[4][tx] = hi;
+    }
+    __syncthreads();
+    for (int s = kDiagNodes / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            red[2][threadIdx.x] += red[2][threadIdx.x + s];
+            red[3][threadIdx.x] = fmin(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kDiagFields; ++k)
+            partial[(size_t)blockIdx.x * kDiagFields + k] = red[k][0];
+    }
+}
+
+__global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(const double* __restrict__ partial,
+                                                                int nblocks, int plane,
+                                                                double* __restrict__ out) {
     __shared__ double red[kDiagFields][kDiagBlock];
+    double err2 = 0.0, spr2 = 0.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
+    for (int b = threadIdx.x; b < nblocks; b += kDiagBlock) {
+        err2 += partial[b * kDiagFields + 0];
+        spr2 += partial[b * kDiagFields + 1];
+        bad += partial[b * kDiagFields + 2];
+        rmin = fmin(rmin, partial[b * kDiagFields + 3]);
+        rmax = fmax(rmax, partial[b * kDiagFields + 4]);
+    }
     red[0][threadIdx.x] = err2;
     red[1][threadIdx.x] = spr2;
     red[2][threadIdx.x] = bad;
@@ -532,29 +716,15 @@ __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int k = 0; k < kDiagFields; ++k) partial[(size_t)blockIdx.x * kDiagFields + k] = red[k][0];
+        out[0] = sqrt(red[0][0] / plane);
+        out[1] = sqrt(red[1][0] / plane);
+        out[2] = red[2][0];
+        out[3] = red[3][0];
+        out[4] = red[4][0];
+        out[5] = 0.0;
+        out[6] = 0.0;
+        out[7] = 0.0;
     }
-}
-
-__global__ void diag_final_kernel(const double* __restrict__ partial, int nblocks, int plane,
-                                  double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double err2 = 0.0, spr2 = 0.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
-    for (int b = 0; b < nblocks; ++b) {
-        err2 += partial[b * kDiagFields + 0];
-        spr2 += partial[b * kDiagFields + 1];
-        bad += partial[b * kDiagFields + 2];
-        rmin = fmin(rmin, partial[b * kDiagFields + 3]);
-        rmax = fmax(rmax, partial[b * kDiagFields + 4]);
-    }
-    out[0] = sqrt(err2 / plane);
-    out[1] = sqrt(spr2 / plane);
-    out[2] = bad;
-    out[3] = rmin;
-    out[4] = rmax;
-    out[5] = 0.0;
-    out[6] = 0.0;
-    out[7] = 0.0;
 }
 
 __global__ void synth_obs_kernel(const double* __restrict__ y, const double* __restrict__ eps,
@@ -564,25 +734,39 @@ __global__ void synth_obs_kernel(const double* __restrict__ y, const double* __r
     if (q < n) yo[q] = y[q] + sigma[q] * eps[q];
 }
 
-template <int N, bool OBS>
-hipError_t launch_one(const AnalysisParams& p, hipStream_t s) {
-    const int nz = p.nvar * p.lmax;
-    const int per_wave = lds_doubles_per_wave(N, nz);
-    const size_t bytes = (size_t)per_wave * sizeof(double);
+template <int N>
+hipError_t launch_obs(const AnalysisParams& p, hipStream_t s) {
+    using L = ObsLayout<N>;
+    const size_t bytes = (size_t)L::total * sizeof(double);
     const int plane = p.nx * p.ny;
-    analysis_kernel<N, OBS><<<plane, 64, bytes, s>>>(p, per_wave, 30);
+    const int blocks = (plane + L::SEGS - 1) / L::SEGS;
+    analysis_obs_kernel<N><<<blocks, 64, bytes, s>>>(p, 30);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_ens(const AnalysisParams& p, hipStream_t s) {
+    const size_t bytes = (size_t)ens_lds_doubles(N, p.nvar * p.lmax) * sizeof(double);
+    const int plane = p.nx * p.ny;
+    if (bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)analysis_ens_kernel<N>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    analysis_ens_kernel<N><<<plane, 64, bytes, s>>>(p, 30);
     return hipGetLastError();
 }
 
 template <bool OBS>
 hipError_t launch_sized(const AnalysisParams& p, int n, hipStream_t s) {
     switch (n) {
-        case 8: return launch_one<8, OBS>(p, s);
-        case 16: return launch_one<16, OBS>(p, s);
-        case 24: return launch_one<24, OBS>(p, s);
-        case 32: return launch_one<32, OBS>(p, s);
-        case 48: return launch_one<48, OBS>(p, s);
-        case 64: return launch_one<64, OBS>(p, s);
+        case 8: return OBS ? launch_obs<8>(p, s) : launch_ens<8>(p, s);
+        case 16: return OBS ? launch_obs<16>(p, s) : launch_ens<16>(p, s);
+        case 24: return OBS ? launch_obs<24>(p, s) : launch_ens<24>(p, s);
+        case 32: return OBS ? launch_obs<32>(p, s) : launch_ens<32>(p, s);
+        case 48: return OBS ? launch_obs<48>(p, s) : launch_ens<48>(p, s);
+        case 64: return OBS ? launch_obs<64>(p, s) : launch_ens<64>(p, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -596,7 +780,20 @@ int analysis_size_for(int n) {
     return 0;
 }
 
-int analysis_lds_bytes(int n, int nz) { return lds_doubles_per_wave(n, nz) * (int)sizeof(double); }
+int analysis_lds_bytes(int n, int nz, int route) {
+    if (route == 2) {
+        switch (n) {
+            case 8: return ObsLayout<8>::total * 8;
+            case 16: return ObsLayout<16>::total * 8;
+            case 24: return ObsLayout<24>::total * 8;
+            case 32: return ObsLayout<32>::total * 8;
+            case 48: return ObsLayout<48>::total * 8;
+            case 64: return ObsLayout<64>::total * 8;
+            default: return 1 << 30;
+        }
+    }
+    return ens_lds_doubles(n, nz) * (int)sizeof(double);
+}
 
 hipError_t launch_observe(const double* f, const int* pts, int npts, int nvar, double* yf,
                           LbmDims d, hipStream_t s) {
@@ -608,7 +805,7 @@ hipError_t launch_observe(const double* f, const int* pts, int npts, int nvar, d
 
 hipError_t launch_obs_stats(const double* yf, const double* yo, int nobs, int members,
                             double* ybar, double* dY, double* dvec, double* K, hipStream_t s) {
-    obs_stats_kernel<<<(nobs + 127) / 128, 128, 0, s>>>(yf, yo, nobs, members, ybar, dY, dvec);
+    obs_stats_kernel<<<(nobs + 3) / 4, 256, 0, s>>>(yf, yo, nobs, members, ybar, dY, dvec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !K) return e;
     const int total = nobs * nobs;
@@ -628,13 +825,16 @@ hipError_t launch_analysis(const AnalysisParams& p, int route, int n, hipStream_
     return route == 2 ? launch_sized<true>(p, n, s) : launch_sized<false>(p, n, s);
 }
 
+int diag_blocks_for(int plane) { return (plane + kDiagNodes - 1) / kDiagNodes; }
+
 hipError_t launch_diag(const double* f, const double* truth_uv, LbmDims d, double* partial,
                        int nblocks, double* out, hipStream_t s) {
-    diag_partial_kernel<<<nblocks, kDiagBlock, 0, s>>>(f, truth_uv, d.nx, d.ny, d.members,
-                                                       partial);
+    const int need = diag_blocks_for(d.nx * d.ny);
+    if (need > nblocks) return hipErrorInvalidValue;
+    diag_partial_kernel<<<need, kDiagBlock, 0, s>>>(f, truth_uv, d.nx, d.ny, d.members, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    diag_final_kernel<<<1, 64, 0, s>>>(partial, nblocks, d.nx * d.ny, out);
+    diag_final_kernel<<<1, kDiagBlock, 0, s>>>(partial, need, d.nx * d.ny, out);
     return hipGetLastError();
 }
 
