@@ -183,6 +183,10 @@ lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs
 lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig_size,
                               int32_t* route);
 
+/* Host-only: hist[k] = number of nodes with exactly k observation points in
+ * their localization support, for k < len (larger counts are not reported). */
+lbmletkf_status lbmletkf_local_histogram(void* ctx, int32_t* hist, int32_t len);
+
 /* Per-stage GPU timing with HIP events on the launch stream.  When enabled,
  * every launch is bracketed by an event pair; lbmletkf_profile_collect waits
  * for them and returns, per stage, the summed milliseconds and launch counts,

@@ -69,6 +69,7 @@ SIGNATURES = {
                                  ctypes.POINTER(_c_int32)]),
     "lbmletkf_info": (_c_int32, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32),
                                  ctypes.POINTER(_c_int32)]),
+    "lbmletkf_local_histogram": (_c_int32, [_vp, ctypes.POINTER(_c_int32), _c_int32]),
     "lbmletkf_set_profiling": (_c_int32, [_vp, _c_int32]),
     "lbmletkf_profile_collect": (_c_int32, [_vp, ctypes.POINTER(_c_double),
                                             ctypes.POINTER(ctypes.c_int64)]),
@@ -306,6 +307,13 @@ class Context:
         _check(load().lbmletkf_moments(self.handle, _dev(f, self.state_numel, "f"), _dev(out),
                                        _stream(stream)))
         return out
+
+    def local_histogram(self) -> np.ndarray:
+        """Nodes per number of local observation points (index = count)."""
+        n = self.n_points + 1
+        buf = (_c_int32 * n)()
+        _check(load().lbmletkf_local_histogram(self.handle, buf, n))
+        return np.array(buf[:], dtype=np.int64)
 
     def set_profiling(self, enable: bool) -> None:
         _check(load().lbmletkf_set_profiling(self.handle, 1 if enable else 0))

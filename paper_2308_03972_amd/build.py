@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmletkf.so")
-SOURCES = ["api.hip", "lbm_kernels.hip", "letkf_kernels.hip"]
+SOURCES = ["api.hip", "lbm_kernels.hip", "letkf_kernels.hip", "letkf_obs.hip"]
 ARCH = os.environ.get("LBMLETKF_ARCH", "gfx950")
 
 
@@ -23,7 +23,7 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every HIP source and link the shared library; returns its path."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

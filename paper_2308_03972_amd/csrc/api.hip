@@ -12,10 +12,6 @@
 
 using namespace lbmletkf;
 
-namespace lbmletkf {
-int analysis_lds_bytes(int n, int nz, int route);
-int diag_blocks_for(int plane);
-}
 
 namespace {
 
@@ -36,7 +32,14 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t fbuf, force, loc_pt, loc_g, pts, ybar, dY, dvec, K, yf, partial, counters, total;
+    size_t fbuf, force, loc_pt, loc_g, pts, ybar, dY, dvec, K, yf, partial, counters, nodes, total;
+};
+
+// Nodes of the observation route grouped by eigenproblem size.
+struct Bucket {
+    int n;       // instantiated eigenproblem size
+    int offset;  // into the device node list
+    int count;
 };
 
 struct Ctx {
@@ -47,6 +50,8 @@ struct Ctx {
     int lmax;
     int route;  // 1 ensemble, 2 observation
     int n_eig;
+    std::vector<Bucket> buckets;
+    std::vector<int> hist;  // nodes per local-point count
     bool has_force;
     char* ws;
     Layout L;
@@ -72,6 +77,7 @@ struct Ctx {
     double* yf() const { return reinterpret_cast<double*>(ws + L.yf); }
     double* partial() const { return reinterpret_cast<double*>(ws + L.partial); }
     int* counters() const { return reinterpret_cast<int*>(ws + L.counters); }
+    int* nodes() const { return reinterpret_cast<int*>(ws + L.nodes); }
 };
 
 // RAII event pair around one launch when profiling is on.
@@ -134,14 +140,19 @@ lbmletkf_status check_obs(const lbmletkf_obs_params* o, const lbmletkf_lbm_param
 
 bool infinite_cut(double d_cut) { return !(d_cut > 0.0) || std::isinf(d_cut); }
 
-// Largest number of observation points inside the localization support of
-// any node; the same criterion (squared distance < (2 d_cut)^2) as the GPU
-// table build, used only for sizing.
-int count_lmax(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o) {
-    if (infinite_cut(o->d_cut)) return o->n_points;
+// Number of observation points inside each node's localization support,
+// with the same criterion (squared distance < (2 d_cut)^2) as the GPU table
+// build; used for sizing and for grouping nodes.  Returns the maximum.
+int local_counts(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o,
+                 std::vector<int>* counts) {
+    const size_t plane = (size_t)p->nx * p->ny;
+    if (counts) counts->assign(plane, 0);
+    if (infinite_cut(o->d_cut)) {
+        if (counts) counts->assign(plane, o->n_points);
+        return o->n_points;
+    }
     const double lim = 4.0 * o->d_cut * o->d_cut;
     int best = 0;
-    std::vector<int> dxs(o->n_points);
     for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
             int cnt = 0;
@@ -151,6 +162,7 @@ int count_lmax(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o) {
                 dy = std::min(dy, p->ny - dy);
                 if ((double)(dx * dx + dy * dy) < lim) ++cnt;
             }
+            if (counts) (*counts)[(size_t)y * p->nx + x] = cnt;
             best = std::max(best, cnt);
         }
     return best;
@@ -162,8 +174,8 @@ int even_up(int n) { return (n + 1) & ~1; }
 lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, int lmax,
                              int* route, int* n) {
     const int nz = o->nvar * lmax;
-    const int nE = analysis_size_for(even_up(p->members));
-    const int nO = analysis_size_for(even_up(nz));
+    const int nE = ens_size_for(even_up(p->members));
+    const int nO = obs_size_for(even_up(nz));
     int r = o->route;
     if (r == LBMLETKF_ROUTE_AUTO) {
         if (nO == 0) r = LBMLETKF_ROUTE_ENSEMBLE;
@@ -173,7 +185,8 @@ lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_pa
     if (sz == 0)
         return fail(LBMLETKF_EUNSUPPORTED,
                     "observation route needs at most 64 local observations per node");
-    if (analysis_lds_bytes(sz, nz, r) > 160 * 1024)
+    const int lds = (r == LBMLETKF_ROUTE_OBSERVATION) ? obs_lds_bytes(sz) : ens_lds_bytes(sz, nz);
+    if (lds > 160 * 1024)
         return fail(LBMLETKF_EUNSUPPORTED, "too many local observations for the LDS budget");
     *route = r;
     *n = sz;
@@ -203,6 +216,7 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
     L.yf = take(nobs * p->members * sizeof(double));
     L.partial = take((size_t)diag_blocks_for((int)plane) * 8 * sizeof(double));
     L.counters = take(16 * sizeof(int));
+    L.nodes = take(plane * sizeof(int));
     L.total = off;
     return L;
 }
@@ -237,7 +251,7 @@ lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
     if (st) return st;
     if ((st = check_obs(obs, lbm))) return st;
     if (!bytes) return fail(LBMLETKF_EINVAL, "bytes is NULL");
-    const int lmax = count_lmax(lbm, obs);
+    const int lmax = local_counts(lbm, obs, nullptr);
     int route = 0, n = 0;
     if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
     *bytes = make_layout(lbm, obs, lmax, route).total;
@@ -249,7 +263,7 @@ lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs
     lbmletkf_status st = check_lbm(lbm);
     if (st) return st;
     if ((st = check_obs(obs, lbm))) return st;
-    const int lmax = count_lmax(lbm, obs);
+    const int lmax = local_counts(lbm, obs, nullptr);
     int r = 0, n = 0;
     if ((st = choose_route(lbm, obs, lmax, &r, &n))) return st;
     if (max_local_points) *max_local_points = lmax;
@@ -268,7 +282,8 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
     *ctx_out = nullptr;
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
         return fail(LBMLETKF_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-    const int lmax = count_lmax(lbm, obs);
+    std::vector<int> counts;
+    const int lmax = local_counts(lbm, obs, &counts);
     int route = 0, n = 0;
     if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
     Layout L = make_layout(lbm, obs, lmax, route);
@@ -286,6 +301,23 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
     c->has_force = d_force != nullptr;
     c->ws = reinterpret_cast<char*>(d_workspace);
     c->L = L;
+    c->hist.assign(lmax + 1, 0);
+    for (int v : counts) c->hist[v] += 1;
+    // group the nodes by the eigenproblem size their local count needs
+    std::vector<int> order;
+    if (route == LBMLETKF_ROUTE_OBSERVATION) {
+        std::vector<std::vector<int>> groups(65);
+        for (size_t i = 0; i < counts.size(); ++i)
+            groups[obs_size_for(even_up(obs->nvar * counts[i]))].push_back((int)i);
+        int maxn = 0;
+        for (int sz = 0; sz <= 64; ++sz) {
+            if (groups[sz].empty()) continue;
+            c->buckets.push_back({sz, (int)order.size(), (int)groups[sz].size()});
+            order.insert(order.end(), groups[sz].begin(), groups[sz].end());
+            maxn = sz;
+        }
+        c->n_eig = maxn;
+    }
     hipStream_t s = as_stream(stream);
     const size_t plane = (size_t)lbm->nx * lbm->ny;
     hipError_t e = hipSuccess;
@@ -296,6 +328,9 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         e = hipMemcpyAsync(c->pts(), obs->points, (size_t)obs->n_points * 2 * sizeof(int),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(c->counters(), 0, 16 * sizeof(int), s);
+    if (e == hipSuccess && !order.empty())
+        e = hipMemcpyAsync(c->nodes(), order.data(), order.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess && lmax > 0)
         e = launch_local_table(c->pts(), obs->n_points, obs->d_cut, lmax, lbm->nx, lbm->ny,
                                c->loc_pt(), c->loc_g(), c->counters(), s);
@@ -414,7 +449,15 @@ lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const 
     p.sqrt_beta = std::sqrt(c->obs.beta);
     p.eig_fail = c->counters() + 1;
     StageTimer t(c, kStageAnalysis, s);
-    hipError_t e = launch_analysis(p, c->route, c->n_eig, s);
+    hipError_t e = hipSuccess;
+    if (c->route == LBMLETKF_ROUTE_OBSERVATION) {
+        for (const Bucket& b : c->buckets) {
+            e = launch_analysis_obs(p, c->nodes() + b.offset, b.count, b.n, s);
+            if (e != hipSuccess) break;
+        }
+    } else {
+        e = launch_analysis_ens(p, c->n_eig, s);
+    }
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "analysis");
 }
 
@@ -467,6 +510,13 @@ lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig
     if (max_local_points) *max_local_points = c->lmax;
     if (eig_size) *eig_size = c->n_eig;
     if (route) *route = c->route;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_local_histogram(void* ctx, int32_t* hist, int32_t len) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !hist || len < 0) return fail(LBMLETKF_EINVAL, "bad argument");
+    for (int k = 0; k < len; ++k) hist[k] = k < (int)c->hist.size() ? c->hist[k] : 0;
     return LBMLETKF_OK;
 }
 

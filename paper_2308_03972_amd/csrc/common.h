@@ -63,9 +63,16 @@ struct AnalysisParams {
     double sqrt_beta;
     int* eig_fail;        // count of nodes whose eigensolver hit the sweep cap
 };
-// route: 1 = ensemble (M x M), 2 = observation (l x l); n = eigenproblem size.
-hipError_t launch_analysis(const AnalysisParams& p, int route, int n, hipStream_t s);
-int analysis_size_for(int n);  // instantiated size >= n, or 0 if none
+// Ensemble route (M x M eigenproblem of size n >= M), every node.
+hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s);
+int ens_size_for(int n);              // instantiated size >= n, or 0
+int ens_lds_bytes(int n, int nz);
+// Observation route (l x l dual, size n >= l) for the `count` nodes listed in `nodes`.
+hipError_t launch_analysis_obs(const AnalysisParams& p, const int* nodes, int count, int n,
+                               hipStream_t s);
+int obs_size_for(int n);              // instantiated size >= n, or 0
+int obs_lds_bytes(int n);
+int diag_blocks_for(int plane);
 
 hipError_t launch_diag(const double* f, const double* truth_uv, LbmDims d, double* partial,
                        int nblocks, double* out, hipStream_t s);

@@ -1,0 +1,161 @@
+// Device helpers shared by the analysis translation units: wave reductions,
+// intra-wave LDS ordering, periodic wrap, XCD-aware block order and the
+// segmented parallel Jacobi eigensolver.
+#pragma once
+#include "common.h"
+
+namespace lbmletkf {
+namespace dev {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Order this wave's LDS writes before its later LDS reads (cross-lane).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Printed Gaspari-Cohn piecewise function, Horner form.
+__device__ __forceinline__ double gaspari_cohn(double d) {
+    if (d <= 1.0) {
+        return (((((-0.25 * d + 0.5) * d + 0.625) * d - 5.0 / 3.0) * d) * d) + 1.0;
+    }
+    if (d < 2.0) {
+        return ((((d / 12.0 - 0.5) * d + 0.625) * d + 5.0 / 3.0) * d - 5.0) * d + 4.0 -
+               (2.0 / 3.0) / d;
+    }
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// wave-level parallel Jacobi on SEGS independent N x N symmetric matrices
+// (N even).  Lane l belongs to segment seg = l / N and holds row i = l % N of
+// its matrix S and of the accumulated rotation matrix U in registers.
+// Round P rotates the pairs (2k+P, 2k+P+1) and swaps them (Brent-Luk
+// ordering): rows are published to LDS, both lanes of a pair read a_pp,
+// a_qq, a_pq from there (so they derive bit-identical rotations), the row
+// mix reads the partner's pre-round row from LDS, and the column mix of S
+// and U is in-register with the pair's (c, s) read back from LDS.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ double extract_lane_entry(const double (&R)[N], int col) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) v = (r == col) ? R[r] : v;
+    return v;
+}
+
+template <int N, int SEGS, int P>
+__device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], double* rows,
+                                             double2* cs, int lane) {
+    constexpr int RS = N;  // row stride (doubles)
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    double* segrows = rows + (size_t)sbase * RS;
+    // publish this lane's row
+    wave_lds_sync();
+    if (active) {
+        double2* my = reinterpret_cast<double2*>(segrows + (size_t)i * RS);
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) my[k] = make_double2(S[2 * k], S[2 * k + 1]);
+    }
+    wave_lds_sync();
+    const bool first = ((i - P) & 1) == 0;
+    const int pi = first ? i + 1 : i - 1;
+    const bool paired = active && pi >= 0 && pi < N;
+    const int p = first ? i : pi;
+    double c = 1.0, s = 0.0;
+    if (paired) {
+        const double app = segrows[(size_t)p * RS + p];
+        const double aqq = segrows[(size_t)(p + 1) * RS + p + 1];
+        const double apq = segrows[(size_t)p * RS + p + 1];
+        if (apq != 0.0) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+            if (theta < 0.0) t = -t;
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+        }
+    }
+    cs[lane] = make_double2(c, s);
+    // rows: S <- P^T J^T S, from the partner's row as published
+    if (paired) {
+        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)pi * RS);
+        const double sg = first ? s : -s;
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) {
+            const double2 v = pr[k];
+            S[2 * k] = c * v.x + sg * S[2 * k];
+            S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
+        }
+    }
+    wave_lds_sync();
+    // columns: S <- S J P, U <- U J P, pair (r, r+1) rotated by its first lane's (c, s)
+#pragma unroll
+    for (int r = P; r + 1 < N; r += 2) {
+        const double2 q = cs[sbase + r];
+        const double a0 = S[r], a1 = S[r + 1];
+        S[r] = q.y * a0 + q.x * a1;
+        S[r + 1] = q.x * a0 - q.y * a1;
+        const double u0 = U[r], u1 = U[r + 1];
+        U[r] = q.y * u0 + q.x * u1;
+        U[r + 1] = q.x * u0 - q.y * u1;
+    }
+}
+
+// Sweeps until every segment's off-diagonal Frobenius norm is below 1e-13
+// of its diagonal norm.  Returns the sweeps used, max_sweeps + 1 if a segment
+// did not converge.  `red` holds 2 doubles per lane.
+template <int N, int SEGS>
+__device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2* cs,
+                          double* red, int lane, int max_sweeps) {
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    for (int sweep = 0;; ++sweep) {
+        double off = 0.0, dg = 0.0;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const double v2 = S[r] * S[r];
+            if (r == i) dg += v2; else off += v2;
+        }
+        wave_lds_sync();
+        red[2 * lane] = active ? off : 0.0;
+        red[2 * lane + 1] = active ? dg : 0.0;
+        wave_lds_sync();
+        double so = 0.0, sd = 0.0;
+        for (int k = 0; k < N; ++k) {
+            so += red[2 * (sbase + k)];
+            sd += red[2 * (sbase + k) + 1];
+        }
+        const bool done = !active || so <= 1e-26 * sd;
+        if (__all(done)) return sweep;
+        if (sweep >= max_sweeps) return max_sweeps + 1;
+#pragma unroll 1
+        for (int rr = 0; rr < N / 2; ++rr) {
+            jacobi_round<N, SEGS, 0>(S, U, rows, cs, lane);
+            jacobi_round<N, SEGS, 1>(S, U, rows, cs, lane);
+        }
+    }
+}
+
+// Block b runs on XCD b % 8; give each XCD a contiguous range of work items
+// so that nodes sharing cache lines meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int per = nblocks / 8;
+    if (b >= per * 8) return b;
+    return (b % 8) * per + b / 8;
+}
+
+}  // namespace dev
+}  // namespace lbmletkf

@@ -22,36 +22,11 @@
 // rotates the neighbour pairs (2k+p, 2k+p+1) and swaps them, so two fixed
 // pairings alternate and every pair meets once per n rounds.
 #include "common.h"
+#include "device_util.h"
 
 namespace lbmletkf {
 namespace {
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
-// Order this wave's LDS writes before its later LDS reads (cross-lane).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-// Printed Gaspari-Cohn piecewise function, Horner form.
-__device__ __forceinline__ double gaspari_cohn(double d) {
-    if (d <= 1.0) {
-        return (((((-0.25 * d + 0.5) * d + 0.625) * d - 5.0 / 3.0) * d) * d) + 1.0;
-    }
-    if (d < 2.0) {
-        return ((((d / 12.0 - 0.5) * d + 0.625) * d + 5.0 / 3.0) * d - 5.0) * d + 4.0 -
-               (2.0 / 3.0) / d;
-    }
-    return 0.0;
-}
+using namespace dev;
 
 // ---------------------------------------------------------------------------
 // observation operator: yf[m][nvar*k + var]
@@ -151,333 +126,6 @@ __global__ void local_table_kernel(const int* __restrict__ pts, int npts, double
     for (int c = cnt; c < lmax; ++c) {
         loc_pt[(size_t)node * lmax + c] = -1;
         loc_g[(size_t)node * lmax + c] = 0.0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// wave-level parallel Jacobi on SEGS independent N x N symmetric matrices
-// (N even).  Lane l belongs to segment seg = l / N and holds row i = l % N of
-// its matrix S and of the accumulated rotation matrix U in registers.
-// Round P rotates the pairs (2k+P, 2k+P+1) and swaps them (Brent-Luk
-// ordering): rows are published to LDS, both lanes of a pair read a_pp,
-// a_qq, a_pq from there (so they derive bit-identical rotations), the row
-// mix reads the partner's pre-round row from LDS, and the column mix of S
-// and U is in-register with the pair's (c, s) read back from LDS.
-// ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ double extract_lane_entry(const double (&R)[N], int col) {
-    double v = 0.0;
-#pragma unroll
-    for (int r = 0; r < N; ++r) v = (r == col) ? R[r] : v;
-    return v;
-}
-
-template <int N, int SEGS, int P>
-__device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], double* rows,
-                                             double2* cs, int lane) {
-    constexpr int RS = N;  // row stride (doubles)
-    const int seg = lane / N;
-    const int i = lane - seg * N;
-    const bool active = seg < SEGS;
-    const int sbase = active ? seg * N : 0;
-    double* segrows = rows + (size_t)sbase * RS;
-    // publish this lane's row
-    wave_lds_sync();
-    if (active) {
-        double2* my = reinterpret_cast<double2*>(segrows + (size_t)i * RS);
-#pragma unroll
-        for (int k = 0; k < N / 2; ++k) my[k] = make_double2(S[2 * k], S[2 * k + 1]);
-    }
-    wave_lds_sync();
-    const bool first = ((i - P) & 1) == 0;
-    const int pi = first ? i + 1 : i - 1;
-    const bool paired = active && pi >= 0 && pi < N;
-    const int p = first ? i : pi;
-    double c = 1.0, s = 0.0;
-    if (paired) {
-        const double app = segrows[(size_t)p * RS + p];
-        const double aqq = segrows[(size_t)(p + 1) * RS + p + 1];
-        const double apq = segrows[(size_t)p * RS + p + 1];
-        if (apq != 0.0) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-            if (theta < 0.0) t = -t;
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-        }
-    }
-    cs[lane] = make_double2(c, s);
-    // rows: S <- P^T J^T S, from the partner's row as published
-    if (paired) {
-        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)pi * RS);
-        const double sg = first ? s : -s;
-#pragma unroll
-        for (int k = 0; k < N / 2; ++k) {
-            const double2 v = pr[k];
-            S[2 * k] = c * v.x + sg * S[2 * k];
-            S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
-        }
-    }
-    wave_lds_sync();
-    // columns: S <- S J P, U <- U J P, pair (r, r+1) rotated by its first lane's (c, s)
-#pragma unroll
-    for (int r = P; r + 1 < N; r += 2) {
-        const double2 q = cs[sbase + r];
-        const double a0 = S[r], a1 = S[r + 1];
-        S[r] = q.y * a0 + q.x * a1;
-        S[r + 1] = q.x * a0 - q.y * a1;
-        const double u0 = U[r], u1 = U[r + 1];
-        U[r] = q.y * u0 + q.x * u1;
-        U[r + 1] = q.x * u0 - q.y * u1;
-    }
-}
-
-// Sweeps until every segment's off-diagonal Frobenius norm is below 1e-13
-// of its diagonal norm.  Returns the sweeps used, max_sweeps + 1 if a segment
-// did not converge.  `red` holds 2 doubles per lane.
-template <int N, int SEGS>
-__device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2* cs,
-                          double* red, int lane, int max_sweeps) {
-    const int seg = lane / N;
-    const int i = lane - seg * N;
-    const bool active = seg < SEGS;
-    const int sbase = active ? seg * N : 0;
-    for (int sweep = 0;; ++sweep) {
-        double off = 0.0, dg = 0.0;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const double v2 = S[r] * S[r];
-            if (r == i) dg += v2; else off += v2;
-        }
-        wave_lds_sync();
-        red[2 * lane] = active ? off : 0.0;
-        red[2 * lane + 1] = active ? dg : 0.0;
-        wave_lds_sync();
-        double so = 0.0, sd = 0.0;
-        for (int k = 0; k < N; ++k) {
-            so += red[2 * (sbase + k)];
-            sd += red[2 * (sbase + k) + 1];
-        }
-        const bool done = !active || so <= 1e-26 * sd;
-        if (__all(done)) return sweep;
-        if (sweep >= max_sweeps) return max_sweeps + 1;
-        for (int rr = 0; rr < N / 2; ++rr) {
-            jacobi_round<N, SEGS, 0>(S, U, rows, cs, lane);
-            jacobi_round<N, SEGS, 1>(S, U, rows, cs, lane);
-        }
-    }
-}
-
-// Block b runs on XCD b % 8; give each XCD a contiguous range of work items
-// so that nodes sharing cache lines meet in the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
-    const int per = nblocks / 8;
-    if (b >= per * 8) return b;
-    return (b % 8) * per + b / 8;
-}
-
-// ---------------------------------------------------------------------------
-// observation route: SEGS = 64 / N nodes per wavefront, eigenproblem Z Z^T
-// ---------------------------------------------------------------------------
-template <int N>
-struct ObsLayout {
-    static constexpr int SEGS = 64 / N;
-    // Jacobi rows, then U, then C; also stages one node's dX (9 x 64)
-    static constexpr int kRows = (SEGS * N * N > 9 * 64 ? SEGS * N * N : 9 * 64) > SEGS * 9 * N
-                                     ? (SEGS * N * N > 9 * 64 ? SEGS * N * N : 9 * 64)
-                                     : SEGS * 9 * N;
-    static constexpr int kB = SEGS * 9 * N;            // B = dX Z^T
-    static constexpr int kE = SEGS * 9 * N;            // E' = phi o (B U)
-    static constexpr int kVec = 4 * 64;                // cs/red during Jacobi; psi, pt, h after
-    static constexpr int kObs = 3 * SEGS * N;          // sw, dt, q
-    static constexpr int kXbar = SEGS * 9 + 1;
-    static constexpr int total = kRows + kB + kE + kVec + kObs + kXbar;
-};
-
-template <int N>
-__global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, int max_sweeps) {
-    using L = ObsLayout<N>;
-    constexpr int SEGS = L::SEGS;
-    extern __shared__ double lds[];
-    double* rows = lds;                              // [SEGS][N][N]
-    double* Bm = rows + L::kRows;                    // [SEGS][9][N]
-    double* Em = Bm + L::kB;                         // [SEGS][9][N]
-    double* vec = Em + L::kE;                        // [4][64]
-    double* sw = vec + L::kVec;                      // [SEGS][N]
-    double* dt = sw + SEGS * N;                      // [SEGS][N]
-    int* qx = reinterpret_cast<int*>(dt + SEGS * N); // [SEGS][N]
-    double* xb = reinterpret_cast<double*>(qx) + SEGS * N;  // [SEGS][9]
-    double2* cs = reinterpret_cast<double2*>(vec);   // Jacobi only
-    double* red = vec + 128;                         // Jacobi only
-
-    const int lane = threadIdx.x;
-    const int nx = p.nx, ny = p.ny, M = p.members;
-    const int plane = nx * ny;
-    const int nz = p.nvar * p.lmax;
-    const int node0 = xcd_remap(blockIdx.x, gridDim.x) * SEGS;
-    const int seg = lane / N;
-    const int i = lane - seg * N;
-    const bool active = seg < SEGS;
-    const int sbase = active ? seg * N : 0;
-    const bool mem = lane < M;
-
-    // ---- phase A (one node at a time, lane = member): x_bar, dX, local
-    //      observations and B = dX Z^T (rows of Z: sqrt(r_j) dY[q_j][:])
-    for (int sg = 0; sg < SEGS; ++sg) {
-        const int node = node0 + sg;
-        const bool valid = node < plane;
-        const int x = valid ? node % nx : 0, y = valid ? node / nx : 0;
-        double dx[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            dx[a] = (valid && mem) ? p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs]
-                                   : 0.0;
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const double xbar = wave_sum(dx[a]) / M;
-            dx[a] = mem ? dx[a] - xbar : 0.0;
-            if (lane == 0) xb[sg * 9 + a] = xbar;
-        }
-        if (lane < N) {
-            int q = 0;
-            double w = 0.0, d = 0.0;
-            if (valid && lane < nz) {
-                const int slot = lane / p.nvar, var = lane - slot * p.nvar;
-                const int k = p.loc_pt[(size_t)node * p.lmax + slot];
-                if (k >= 0) {
-                    q = k * p.nvar + var;
-                    w = sqrt(p.loc_g[(size_t)node * p.lmax + slot] * p.rinv[var]);
-                    d = w * p.dvec[q];
-                }
-            }
-            qx[sg * N + lane] = q;
-            sw[sg * N + lane] = w;
-            dt[sg * N + lane] = d;
-        }
-        // stage dX of this node in the (not yet used) Jacobi rows area
-        wave_lds_sync();
-#pragma unroll
-        for (int a = 0; a < 9; ++a) rows[a * 64 + lane] = dx[a];
-        wave_lds_sync();
-        if (lane < N) {
-            double b[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) b[a] = 0.0;
-            const double wj = sw[sg * N + lane];
-            if (wj != 0.0) {
-                const double* yrow = p.dY + (size_t)qx[sg * N + lane] * M;
-                for (int m = 0; m < M; ++m) {
-                    const double yv = yrow[m];
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) b[a] += rows[a * 64 + m] * yv;
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 9; ++a) Bm[(sg * 9 + a) * N + lane] = b[a] * wj;
-        }
-    }
-    wave_lds_sync();
-
-    // ---- phase B: S = Z Z^T = diag(sw) K diag(sw) on the local observations
-    double S[N], U[N];
-    {
-        const double wi = active ? sw[sbase + i] : 0.0;
-        const double* Krow = p.K + (size_t)(active ? qx[sbase + i] : 0) * p.nobs;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const double wk = sw[sbase + k];
-            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * Krow[qx[sbase + k]] : 0.0;
-            U[k] = (k == i && active) ? 1.0 : 0.0;
-        }
-    }
-
-    // ---- phase C: eigendecomposition
-    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, max_sweeps);
-    if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
-
-    // ---- phase D: eigenvalue functions, U to LDS, t = U^T d~, h = U psi t
-    const double lam = extract_lane_entry<N>(S, i);
-    const double sq = sqrt(1.0 + lam / p.a);
-    const double psi = 1.0 / (p.a + lam);
-    const double phi = -p.sqrt_beta / (p.a * sq * (1.0 + sq));
-    double* pt = vec;          // psi_c t_c
-    double* hv = vec + 64;     // h_j
-    wave_lds_sync();
-    if (active) {
-        double2* my = reinterpret_cast<double2*>(rows + (size_t)(sbase + i) * N);
-#pragma unroll
-        for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
-    }
-    wave_lds_sync();
-    {
-        double t = 0.0;
-        if (active)
-            for (int k = 0; k < N; ++k) t += rows[(size_t)(sbase + k) * N + i] * dt[sbase + k];
-        pt[lane] = active ? psi * t : 0.0;
-    }
-    wave_lds_sync();
-    {
-        double h = 0.0;
-#pragma unroll
-        for (int c = 0; c < N; ++c) h += U[c] * pt[sbase + c];
-        hv[lane] = active ? h : 0.0;
-    }
-    // ---- phase E: E' = phi o (B U)
-    if (active) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double e = 0.0;
-            for (int k = 0; k < N; ++k)
-                e += Bm[(seg * 9 + a) * N + k] * rows[(size_t)(sbase + k) * N + i];
-            Em[(seg * 9 + a) * N + i] = phi * e;
-        }
-    }
-    wave_lds_sync();
-    // ---- phase F: C = E' U^T (own row of U), into the rows area
-    if (active) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double cj = 0.0;
-#pragma unroll
-            for (int c = 0; c < N; ++c) cj += Em[(seg * 9 + a) * N + c] * U[c];
-            rows[(seg * 9 + a) * N + i] = cj;
-        }
-    }
-    wave_lds_sync();
-
-    // ---- phase G (one node at a time, lane = member): apply and store
-    for (int sg = 0; sg < SEGS; ++sg) {
-        const int node = node0 + sg;
-        if (node >= plane) break;
-        const int x = node % nx, y = node / nx;
-        double dm[9], acc[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            dm[a] = 0.0;
-            acc[a] = 0.0;
-        }
-        for (int j = 0; j < N; ++j) {
-            const double wj = sw[sg * N + j];
-            const double hj = hv[sg * N + j];
-            const double z = (mem && wj != 0.0) ? wj * p.dY[(size_t)qx[sg * N + j] * M + lane] : 0.0;
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                dm[a] += Bm[(sg * 9 + a) * N + j] * hj;
-                acc[a] += rows[(sg * 9 + a) * N + j] * z;
-            }
-        }
-        if (mem) {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-                double* slot = p.f + ((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs;
-                const double fa = *slot;
-                const double xbar = xb[sg * 9 + a];
-                *slot = xbar + p.sqrt_beta * (fa - xbar) + dm[a] + acc[a];
-            }
-        }
     }
 }
 
@@ -735,16 +383,6 @@ __global__ void synth_obs_kernel(const double* __restrict__ y, const double* __r
 }
 
 template <int N>
-hipError_t launch_obs(const AnalysisParams& p, hipStream_t s) {
-    using L = ObsLayout<N>;
-    const size_t bytes = (size_t)L::total * sizeof(double);
-    const int plane = p.nx * p.ny;
-    const int blocks = (plane + L::SEGS - 1) / L::SEGS;
-    analysis_obs_kernel<N><<<blocks, 64, bytes, s>>>(p, 30);
-    return hipGetLastError();
-}
-
-template <int N>
 hipError_t launch_ens(const AnalysisParams& p, hipStream_t s) {
     const size_t bytes = (size_t)ens_lds_doubles(N, p.nvar * p.lmax) * sizeof(double);
     const int plane = p.nx * p.ny;
@@ -758,42 +396,28 @@ hipError_t launch_ens(const AnalysisParams& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool OBS>
-hipError_t launch_sized(const AnalysisParams& p, int n, hipStream_t s) {
+hipError_t launch_ens_sized(const AnalysisParams& p, int n, hipStream_t s) {
     switch (n) {
-        case 8: return OBS ? launch_obs<8>(p, s) : launch_ens<8>(p, s);
-        case 16: return OBS ? launch_obs<16>(p, s) : launch_ens<16>(p, s);
-        case 24: return OBS ? launch_obs<24>(p, s) : launch_ens<24>(p, s);
-        case 32: return OBS ? launch_obs<32>(p, s) : launch_ens<32>(p, s);
-        case 48: return OBS ? launch_obs<48>(p, s) : launch_ens<48>(p, s);
-        case 64: return OBS ? launch_obs<64>(p, s) : launch_ens<64>(p, s);
+        case 8: return launch_ens<8>(p, s);
+        case 16: return launch_ens<16>(p, s);
+        case 24: return launch_ens<24>(p, s);
+        case 32: return launch_ens<32>(p, s);
+        case 48: return launch_ens<48>(p, s);
+        case 64: return launch_ens<64>(p, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int analysis_size_for(int n) {
+int ens_size_for(int n) {
     const int sizes[] = {8, 16, 24, 32, 48, 64};
     for (int v : sizes)
         if (n <= v) return v;
     return 0;
 }
 
-int analysis_lds_bytes(int n, int nz, int route) {
-    if (route == 2) {
-        switch (n) {
-            case 8: return ObsLayout<8>::total * 8;
-            case 16: return ObsLayout<16>::total * 8;
-            case 24: return ObsLayout<24>::total * 8;
-            case 32: return ObsLayout<32>::total * 8;
-            case 48: return ObsLayout<48>::total * 8;
-            case 64: return ObsLayout<64>::total * 8;
-            default: return 1 << 30;
-        }
-    }
-    return ens_lds_doubles(n, nz) * (int)sizeof(double);
-}
+int ens_lds_bytes(int n, int nz) { return ens_lds_doubles(n, nz) * (int)sizeof(double); }
 
 hipError_t launch_observe(const double* f, const int* pts, int npts, int nvar, double* yf,
                           LbmDims d, hipStream_t s) {
@@ -821,8 +445,8 @@ hipError_t launch_local_table(const int* pts, int npts, double d_cut, int lmax, 
     return hipGetLastError();
 }
 
-hipError_t launch_analysis(const AnalysisParams& p, int route, int n, hipStream_t s) {
-    return route == 2 ? launch_sized<true>(p, n, s) : launch_sized<false>(p, n, s);
+hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s) {
+    return launch_ens_sized(p, n, s);
 }
 
 int diag_blocks_for(int plane) { return (plane + kDiagNodes - 1) / kDiagNodes; }
