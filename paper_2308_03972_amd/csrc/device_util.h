@@ -79,10 +79,12 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
         const double aqq = segrows[(size_t)(p + 1) * RS + p + 1];
         const double apq = segrows[(size_t)p * RS + p + 1];
         if (apq != 0.0) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-            if (theta < 0.0) t = -t;
-            c = 1.0 / sqrt(1.0 + t * t);
+            // smaller root of t^2 + 2 tau t - 1 = 0, tau = (aqq - app) / (2 apq), written
+            // without forming tau: t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app
+            const double d = aqq - app;
+            const double den = fabs(d) + sqrt(d * d + 4.0 * apq * apq);
+            const double t = (d < 0.0 ? -2.0 * apq : 2.0 * apq) / den;
+            c = rsqrt(1.0 + t * t);
             s = t * c;
         }
     }

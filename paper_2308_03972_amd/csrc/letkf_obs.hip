@@ -27,16 +27,15 @@ using namespace dev;
 template <int N>
 struct ObsLayout {
     static constexpr int SEGS = 64 / N;
-    // Jacobi rows, then U, then C; also stages one node's dX (9 x 64)
-    static constexpr int kRows = (SEGS * N * N > 9 * 64 ? SEGS * N * N : 9 * 64) > SEGS * 9 * N
-                                     ? (SEGS * N * N > 9 * 64 ? SEGS * N * N : 9 * 64)
-                                     : SEGS * 9 * N;
-    static constexpr int kB = SEGS * 9 * N;            // B = dX Z^T
-    static constexpr int kE = SEGS * 9 * N;            // E' = phi o (B U)
-    static constexpr int kVec = 4 * 64;                // cs/red during Jacobi; psi, pt, h after
-    static constexpr int kObs = 3 * SEGS * N;          // sw, dt, q
+    static constexpr int cmax(int x, int y) { return x > y ? x : y; }
+    // Jacobi rows; stages one node's dX (9 x 64) before, holds E' after
+    static constexpr int kRows = cmax(cmax(SEGS * N * N, 9 * 64), SEGS * 9 * N);
+    // per segment 10 N doubles: B = dX Z^T as [9][N], later C as [N][10]
+    static constexpr int kBC = SEGS * 10 * N;
+    static constexpr int kVec = 4 * 64;  // cs|red during Jacobi; psi t, h, mean increment after
+    static constexpr int kObs = 2 * SEGS * N + (SEGS * N + 1) / 2;  // sw, dt, q
     static constexpr int kXbar = SEGS * 9 + 1;
-    static constexpr int total = kRows + kB + kE + kVec + kObs + kXbar;
+    static constexpr int total = kRows + kBC + kVec + kObs + kXbar;
 };
 
 template <int N>
@@ -46,15 +45,17 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     constexpr int SEGS = L::SEGS;
     extern __shared__ double lds[];
     double* rows = lds;                              // [SEGS][N][N]
-    double* Bm = rows + L::kRows;                    // [SEGS][9][N]
-    double* Em = Bm + L::kB;                         // [SEGS][9][N]
-    double* vec = Em + L::kE;                        // [4][64]
+    double* BC = rows + L::kRows;                    // [SEGS][10 N]
+    double* vec = BC + L::kBC;                       // [4][64]
     double* sw = vec + L::kVec;                      // [SEGS][N]
     double* dt = sw + SEGS * N;                      // [SEGS][N]
     int* qx = reinterpret_cast<int*>(dt + SEGS * N); // [SEGS][N]
-    double* xb = reinterpret_cast<double*>(qx) + SEGS * N;  // [SEGS][9]
+    double* xb = rows + L::kRows + L::kBC + L::kVec + L::kObs;  // [SEGS][9]
     double2* cs = reinterpret_cast<double2*>(vec);   // Jacobi only
     double* red = vec + 128;                         // Jacobi only
+    double* pt = vec;                                // psi_c t_c
+    double* hv = vec + 64;                           // h_j
+    double* dmv = vec + 128;                         // [SEGS][9] dX w_bar
 
     const int lane = threadIdx.x;
     const int nx = p.nx, ny = p.ny, M = p.members;
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     const bool active = seg < SEGS;
     const int sbase = active ? seg * N : 0;
     const bool mem = lane < M;
+    const int mchunk = (M + SEGS - 1) / SEGS;  // members per lane group in B
 
     // ---- phase A (one node at a time, lane = member): x_bar, dX, local
     //      observations and B = dX Z^T (rows of Z: sqrt(r_j) dY[q_j][:])
@@ -87,6 +89,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
             dx[a] = mem ? dx[a] - xbar : 0.0;
             if (lane == 0) xb[sg * 9 + a] = xbar;
         }
+        wave_lds_sync();
         if (lane < N) {
             int q = 0;
             double w = 0.0, d = 0.0;
@@ -103,30 +106,45 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
             sw[sg * N + lane] = w;
             dt[sg * N + lane] = d;
         }
-        // stage dX of this node in the (not yet used) Jacobi rows area
-        wave_lds_sync();
+        // stage dX of this node ([a][m]) in the not yet used Jacobi rows area
 #pragma unroll
         for (int a = 0; a < 9; ++a) rows[a * 64 + lane] = dx[a];
         wave_lds_sync();
-        if (lane < N) {
-            double b[9];
+        // lane (g, j): partial sum of B[a][j] over member group g
+        double b[9];
 #pragma unroll
-            for (int a = 0; a < 9; ++a) b[a] = 0.0;
-            const double wj = sw[sg * N + lane];
+        for (int a = 0; a < 9; ++a) b[a] = 0.0;
+        if (active) {
+            const double wj = sw[sg * N + i];
             if (wj != 0.0) {
-                const double* yrow = p.dY + (size_t)qx[sg * N + lane] * M;
-#pragma unroll 4
-                for (int m = 0; m < M; ++m) {
+                const double* yrow = p.dY + (size_t)qx[sg * N + i] * M;
+                const int m0 = seg * mchunk;
+                const int m1 = min(M, m0 + mchunk);
+#pragma unroll 2
+                for (int m = m0; m < m1; ++m) {
                     const double yv = yrow[m];
 #pragma unroll
                     for (int a = 0; a < 9; ++a) b[a] += rows[a * 64 + m] * yv;
                 }
             }
-#pragma unroll
-            for (int a = 0; a < 9; ++a) Bm[(sg * 9 + a) * N + lane] = b[a] * wj;
         }
+        // combine the member groups in a fixed order (group 0 keeps the sum)
+#pragma unroll
+        for (int g = 1; g < SEGS; ++g) {
+            const int src = i + g * N;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const double v = __shfl(b[a], active ? src : lane, kWave);
+                b[a] += (seg == 0) ? v : 0.0;
+            }
+        }
+        if (lane < N) {
+            const double wj = sw[sg * N + lane];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) BC[sg * 10 * N + a * N + lane] = b[a] * wj;
+        }
+        wave_lds_sync();
     }
-    wave_lds_sync();
 
     // ---- phase B: S = Z Z^T = diag(sw) K diag(sw) on the local observations
     double S[N], U[N];
@@ -150,8 +168,6 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     const double sq = sqrt(1.0 + lam / p.a);
     const double psi = 1.0 / (p.a + lam);
     const double phi = -p.sqrt_beta / (p.a * sq * (1.0 + sq));
-    double* pt = vec;          // psi_c t_c
-    double* hv = vec + 64;     // h_j
     wave_lds_sync();
     if (active) {
         double2* my = reinterpret_cast<double2*>(rows + (size_t)(sbase + i) * N);
@@ -172,26 +188,48 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
         for (int c = 0; c < N; ++c) h += U[c] * pt[sbase + c];
         hv[lane] = active ? h : 0.0;
     }
-    // ---- phase E: E' = phi o (B U)
-    if (active) {
+    // ---- phase E: e = (B U)[:, i]; mean increment dm = B h (lanes a < 9)
+    double e[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double e = 0.0;
-            for (int k = 0; k < N; ++k)
-                e += Bm[(seg * 9 + a) * N + k] * rows[(size_t)(sbase + k) * N + i];
-            Em[(seg * 9 + a) * N + i] = phi * e;
+    for (int a = 0; a < 9; ++a) e[a] = 0.0;
+    if (active) {
+        const double* Bs = BC + seg * 10 * N;
+        for (int k = 0; k < N; ++k) {
+            const double ukc = rows[(size_t)(sbase + k) * N + i];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) e[a] += Bs[a * N + k] * ukc;
         }
     }
-    wave_lds_sync();
-    // ---- phase F: C = E' U^T (own row of U), into the rows area
+    wave_lds_sync();  // h visible
+    double dm = 0.0;
+    if (active && i < 9) {
+        const double* Bs = BC + seg * 10 * N + i * N;
+        for (int j = 0; j < N; ++j) dm += Bs[j] * hv[sbase + j];
+    }
+    wave_lds_sync();  // all reads of U (rows) done
     if (active) {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double cj = 0.0;
+        for (int a = 0; a < 9; ++a) rows[(seg * 9 + a) * N + i] = phi * e[a];  // E'
+        if (i < 9) dmv[seg * 9 + i] = dm;
+    }
+    wave_lds_sync();
+    // ---- phase F: C = E' U^T (own row of U)
+    double cj[9];
 #pragma unroll
-            for (int c = 0; c < N; ++c) cj += Em[(seg * 9 + a) * N + c] * U[c];
-            rows[(seg * 9 + a) * N + i] = cj;
+    for (int a = 0; a < 9; ++a) {
+        double acc = 0.0;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc += rows[(seg * 9 + a) * N + c] * U[c];
         }
+        cj[a] = acc;
+    }
+    wave_lds_sync();  // all reads of B done (phase E) -- overwrite with C
+    if (active) {
+        double* Cj = BC + seg * 10 * N + i * 10;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) Cj[a] = cj[a];
+        Cj[9] = 0.0;
     }
     wave_lds_sync();
 
@@ -201,21 +239,20 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
         if (item0 + sg >= count) break;
         const int node = nodes[item0 + sg];
         const int x = node % nx, y = node / nx;
-        double dm[9], acc[9];
+        double acc[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            dm[a] = 0.0;
-            acc[a] = 0.0;
-        }
+        for (int a = 0; a < 9; ++a) acc[a] = 0.0;
+        const double* Cs = BC + sg * 10 * N;
 #pragma unroll 2
         for (int j = 0; j < N; ++j) {
             const double wj = sw[sg * N + j];
-            const double hj = hv[sg * N + j];
             const double z = (mem && wj != 0.0) ? wj * p.dY[(size_t)qx[sg * N + j] * M + lane] : 0.0;
+            const double2* c2 = reinterpret_cast<const double2*>(Cs + j * 10);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                dm[a] += Bm[(sg * 9 + a) * N + j] * hj;
-                acc[a] += rows[(sg * 9 + a) * N + j] * z;
+            for (int h = 0; h < 5; ++h) {
+                const double2 v = c2[h];
+                acc[2 * h] += v.x * z;
+                if (2 * h + 1 < 9) acc[2 * h + 1] += v.y * z;
             }
         }
         if (mem) {
@@ -225,7 +262,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
                 double* slot = p.f + ((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs;
                 const double fa = *slot;
                 const double xbar = xb[sg * 9 + a];
-                *slot = xbar + p.sqrt_beta * (fa - xbar) + dm[a] + acc[a];
+                *slot = xbar + p.sqrt_beta * (fa - xbar) + dmv[sg * 9 + a] + acc[a];
             }
         }
     }
