@@ -26,6 +26,7 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 template <int N>
 struct ObsLayout {
+    static_assert(N >= 8 && N % 2 == 0, "eigenproblem size must be even and >= 8");
     static constexpr int SEGS = 64 / N;
     static constexpr int cmax(int x, int y) { return x > y ? x : y; }
     // Jacobi rows; stages one node's dX (9 x 64) before, holds E' after
@@ -201,16 +202,25 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
         }
     }
     wave_lds_sync();  // h visible
-    double dm = 0.0;
-    if (active && i < 9) {
-        const double* Bs = BC + seg * 10 * N + i * N;
-        for (int j = 0; j < N; ++j) dm += Bs[j] * hv[sbase + j];
+    // population a = i, i + N, ... of the mean increment (N may be < 9)
+    double dm[2] = {0.0, 0.0};
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int a = i + r * N;
+            if (a < 9) {
+                const double* Bs = BC + seg * 10 * N + a * N;
+                for (int j = 0; j < N; ++j) dm[r] += Bs[j] * hv[sbase + j];
+            }
+        }
     }
     wave_lds_sync();  // all reads of U (rows) done
     if (active) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) rows[(seg * 9 + a) * N + i] = phi * e[a];  // E'
-        if (i < 9) dmv[seg * 9 + i] = dm;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            if (i + r * N < 9) dmv[seg * 9 + i + r * N] = dm[r];
     }
     wave_lds_sync();
     // ---- phase F: C = E' U^T (own row of U)
