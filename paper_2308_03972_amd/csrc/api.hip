@@ -1,6 +1,7 @@
 // C-ABI layer of liblbmletkf: argument validation, workspace carving, stream
 // ordering of the launches and per-stage timing.  Declarations and the
 // contract of every entry point are in include/lbmletkf.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,6 +52,11 @@ struct Ctx {
     int route;  // 1 ensemble, 2 observation
     int n_eig;
     std::vector<Bucket> buckets;
+    // side streams that run the smaller node groups concurrently with the largest
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {nullptr, nullptr, nullptr};
     std::vector<int> hist;  // nodes per local-point count
     bool has_force;
     char* ws;
@@ -222,6 +228,17 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
 }
 
 Ctx* as_ctx(void* c) { return reinterpret_cast<Ctx*>(c); }
+
+void release_streams(Ctx* c) {
+    for (int k = 0; k < Ctx::kSide; ++k) {
+        if (c->side[k]) (void)hipStreamDestroy(c->side[k]);
+        if (c->join[k]) (void)hipEventDestroy(c->join[k]);
+        c->side[k] = nullptr;
+        c->join[k] = nullptr;
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    c->fork = nullptr;
+}
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
@@ -317,6 +334,9 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
             maxn = sz;
         }
         c->n_eig = maxn;
+        // largest group first: it stays on the caller's stream
+        std::stable_sort(c->buckets.begin(), c->buckets.end(),
+                         [](const Bucket& a, const Bucket& b) { return a.count > b.count; });
     }
     hipStream_t s = as_stream(stream);
     const size_t plane = (size_t)lbm->nx * lbm->ny;
@@ -328,6 +348,13 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         e = hipMemcpyAsync(c->pts(), obs->points, (size_t)obs->n_points * 2 * sizeof(int),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(c->counters(), 0, 16 * sizeof(int), s);
+    if (e == hipSuccess && c->buckets.size() > 1) {
+        e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+        for (int k = 0; k < Ctx::kSide && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming);
+        }
+    }
     if (e == hipSuccess && !order.empty())
         e = hipMemcpyAsync(c->nodes(), order.data(), order.size() * sizeof(int),
                            hipMemcpyHostToDevice, s);
@@ -339,10 +366,12 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         e = hipMemcpyAsync(&overflow, c->counters(), sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+        release_streams(c);
         delete c;
         return hip_fail(e, "lbmletkf_create");
     }
     if (overflow != 0) {
+        release_streams(c);
         delete c;
         return fail(LBMLETKF_EINVAL, "local-observation table overflow");
     }
@@ -357,6 +386,7 @@ lbmletkf_status lbmletkf_destroy(void* ctx) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }
+    release_streams(c);
     delete c;
     return LBMLETKF_OK;
 }
@@ -451,9 +481,20 @@ lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const 
     StageTimer t(c, kStageAnalysis, s);
     hipError_t e = hipSuccess;
     if (c->route == LBMLETKF_ROUTE_OBSERVATION) {
-        for (const Bucket& b : c->buckets) {
-            e = launch_analysis_obs(p, c->nodes() + b.offset, b.count, b.n, s);
-            if (e != hipSuccess) break;
+        // the largest group on the caller's stream, the others forked onto the
+        // side streams after everything queued so far, then joined back
+        const int nb = (int)c->buckets.size();
+        if (nb > 1) e = hipEventRecord(c->fork, s);
+        for (int k = 1; k < nb && e == hipSuccess && k <= Ctx::kSide; ++k)
+            e = hipStreamWaitEvent(c->side[k - 1], c->fork, 0);
+        for (int k = 0; k < nb && e == hipSuccess; ++k) {
+            const Bucket& b = c->buckets[k];
+            hipStream_t sk = k == 0 ? s : c->side[(k - 1) % Ctx::kSide];
+            e = launch_analysis_obs(p, c->nodes() + b.offset, b.count, b.n, sk);
+        }
+        for (int k = 1; k < nb && e == hipSuccess && k <= Ctx::kSide; ++k) {
+            e = hipEventRecord(c->join[k - 1], c->side[k - 1]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join[k - 1], 0);
         }
     } else {
         e = launch_analysis_ens(p, c->n_eig, s);
