@@ -35,6 +35,27 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
 BYTES_PER_NODE_MEMBER = 144.0  # 9 loads + 9 stores of FP64 per node and member
 
 
+def traffic_record(kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 PMC summary in
+    profiles/ (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy), or
+    None when the kernel's sources changed after the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record:"):
+                continue
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel") != kernel:
+                continue
+            h = hashlib.sha256()
+            for src in rec["sources"]:
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+            if h.hexdigest() == rec["sources_sha256"]:
+                return rec
+    return None
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -187,9 +208,12 @@ def main() -> int:
     n_local = cfg.nvar * ectx.max_local_points
     an_flops = analysis_flops_per_node(ectx.route, cfg.members, n_local, ectx.eig_size) * plane
     an_tflops = an_flops / t_an / 1e12
+    rec = traffic_record("stream_collide_kernel") if cfg.name == "paper" else None
     rl_lbm = {"kernel": "stream_collide", "bound": "hbm", "achieved": round(lbm_gbs, 1),
               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(lbm_gbs / HBM_PEAK_GBS, 4),
-              "traffic": None, "avg_launch_us": round(per_launch["stream_collide"] * 1e3, 2)}
+              "traffic": rec["bytes_per_launch"] if rec else None,
+              "algorithmic_bytes": int(BYTES_PER_NODE_MEMBER * plane * cfg.members),
+              "avg_launch_us": round(per_launch["stream_collide"] * 1e3, 2)}
     rl_an = {"kernel": "analysis", "bound": "alu", "achieved": round(an_tflops, 3),
              "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
              "frac": round(an_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None,

@@ -52,10 +52,17 @@ __device__ __forceinline__ double extract_lane_entry(const double (&R)[N], int c
     return v;
 }
 
+// Row stride (doubles) of the Jacobi row exchange: 16 lanes reading 16-byte
+// pieces of consecutive rows hit distinct LDS banks when stride/2 is odd.
+template <int N>
+struct RowStride {
+    static constexpr int value = (N % 4 == 2) ? N : N + 2;
+};
+
 template <int N, int SEGS, int P>
 __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], double* rows,
                                              double2* cs, int lane) {
-    constexpr int RS = N;  // row stride (doubles)
+    constexpr int RS = RowStride<N>::value;
     const int seg = lane / N;
     const int i = lane - seg * N;
     const bool active = seg < SEGS;

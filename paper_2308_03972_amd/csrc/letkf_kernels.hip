@@ -135,7 +135,8 @@ __global__ void local_table_kernel(const int* __restrict__ pts, int npts, double
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int ens_lds_doubles(int n, int nz) {
     const int nzp = (nz + 1) & ~1;
-    return 9 * 64 + n * n + 4 * 64 + 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
+    const int rs = (n % 4 == 2) ? n : n + 2;
+    return 9 * 64 + n * rs + 4 * 64 + 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
 }
 
 template <int N>
@@ -149,8 +150,9 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
     const int nz = p.nvar * p.lmax;
     const int nzp = (nz + 1) & ~1;
     double* sdx = lds;                   // [9][64]
-    double* rows = sdx + 9 * 64;         // [N][N]  Jacobi rows, then U
-    double* vec = rows + N * N;          // [4][64]
+    constexpr int RS = RowStride<N>::value;
+    double* rows = sdx + 9 * 64;         // [N][RS]  Jacobi rows, then U
+    double* vec = rows + N * RS;         // [4][64]
     double* se = vec + 4 * 64;           // [9][N]
     double* zr = se + 9 * N;             // [64]
     double* sw = zr + 64;                // [nz]
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
     wave_lds_sync();
     gv[lane] = g;
     if (lane < N) {
-        double2* my = reinterpret_cast<double2*>(rows + (size_t)lane * N);
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)lane * RS);
 #pragma unroll
         for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
     }
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
     for (int a = 0; a < 9; ++a) e[a] = 0.0;
     if (lane < N) {
         for (int k = 0; k < N; ++k) {
-            const double ukc = rows[(size_t)k * N + lane];
+            const double ukc = rows[(size_t)k * RS + lane];
             t += ukc * gv[k];
 #pragma unroll
             for (int a = 0; a < 9; ++a) e[a] += sdx[a * 64 + k] * ukc;

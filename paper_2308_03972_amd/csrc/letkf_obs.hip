@@ -30,7 +30,8 @@ struct ObsLayout {
     static constexpr int SEGS = 64 / N;
     static constexpr int cmax(int x, int y) { return x > y ? x : y; }
     // Jacobi rows; stages one node's dX (9 x 64) before, holds E' after
-    static constexpr int kRows = cmax(cmax(SEGS * N * N, 9 * 64), SEGS * 9 * N);
+    static constexpr int RS = RowStride<N>::value;
+    static constexpr int kRows = cmax(cmax(SEGS * N * RS, 9 * 64), SEGS * 9 * N);
     // per segment 10 N doubles: B = dX Z^T as [9][N], later C as [N][10]
     static constexpr int kBC = SEGS * 10 * N;
     static constexpr int kVec = 4 * 64;  // cs|red during Jacobi; psi t, h, mean increment after
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     using L = ObsLayout<N>;
     constexpr int SEGS = L::SEGS;
     extern __shared__ double lds[];
-    double* rows = lds;                              // [SEGS][N][N]
+    double* rows = lds;                              // [SEGS][N][RS]
+    constexpr int RS = L::RS;
     double* BC = rows + L::kRows;                    // [SEGS][10 N]
     double* vec = BC + L::kBC;                       // [4][64]
     double* sw = vec + L::kVec;                      // [SEGS][N]
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     const double phi = -p.sqrt_beta / (p.a * sq * (1.0 + sq));
     wave_lds_sync();
     if (active) {
-        double2* my = reinterpret_cast<double2*>(rows + (size_t)(sbase + i) * N);
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)(sbase + i) * RS);
 #pragma unroll
         for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
     }
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     {
         double t = 0.0;
         if (active)
-            for (int k = 0; k < N; ++k) t += rows[(size_t)(sbase + k) * N + i] * dt[sbase + k];
+            for (int k = 0; k < N; ++k) t += rows[(size_t)(sbase + k) * RS + i] * dt[sbase + k];
         pt[lane] = active ? psi * t : 0.0;
     }
     wave_lds_sync();
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
     if (active) {
         const double* Bs = BC + seg * 10 * N;
         for (int k = 0; k < N; ++k) {
-            const double ukc = rows[(size_t)(sbase + k) * N + i];
+            const double ukc = rows[(size_t)(sbase + k) * RS + i];
 #pragma unroll
             for (int a = 0; a < 9; ++a) e[a] += Bs[a * N + k] * ukc;
         }
