@@ -67,16 +67,20 @@ __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
     const double* __restrict__ b = fin + (size_t)m * 9 * plane;
     const int rc = y * nx, rm = ym * nx, rp = yp * nx;
+    // every population is read once and written once per step: stream it
+    // past the caches (nontemporal loads and stores)
+    const size_t src[9] = {(size_t)rc + x,
+                           (size_t)1 * plane + rc + xm,
+                           (size_t)2 * plane + rc + xp,
+                           (size_t)3 * plane + rm + x,
+                           (size_t)4 * plane + rp + x,
+                           (size_t)5 * plane + rm + xm,
+                           (size_t)6 * plane + rp + xp,
+                           (size_t)7 * plane + rp + xm,
+                           (size_t)8 * plane + rm + xp};
     double f[9];
-    f[0] = b[rc + x];
-    f[1] = b[(size_t)1 * plane + rc + xm];
-    f[2] = b[(size_t)2 * plane + rc + xp];
-    f[3] = b[(size_t)3 * plane + rm + x];
-    f[4] = b[(size_t)4 * plane + rp + x];
-    f[5] = b[(size_t)5 * plane + rm + xm];
-    f[6] = b[(size_t)6 * plane + rp + xp];
-    f[7] = b[(size_t)7 * plane + rp + xm];
-    f[8] = b[(size_t)8 * plane + rm + xp];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) f[a] = __builtin_nontemporal_load(b + src[a]);
     double fx = 0.0, fy = 0.0;
     if (force) {
         fx = force[i];
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
     collide_node(f, tau0, smag, fx, fy, mu);
     double* __restrict__ o = fout + (size_t)m * 9 * plane + i;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) o[(size_t)a * plane] = f[a];
+    for (int a = 0; a < 9; ++a) __builtin_nontemporal_store(f[a], o + (size_t)a * plane);
 }
 
 // storage slot (a, y, x) <- canonical (a, y + c_ay, x + c_ax)
