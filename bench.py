@@ -111,6 +111,8 @@ def main() -> int:
     ap.add_argument("--config", default="paper")
     ap.add_argument("--route", default="auto", choices=["auto", "ensemble", "observation"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision form (FP32 population storage) comparison")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--cpu-nodes", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -164,33 +166,47 @@ def main() -> int:
         ytrue = tctx.observe(ft)[0].contiguous()
         yo_all[c] = binding.synth_obs(ytrue, noise[c].contiguous(), sig)
         tuv_all[c] = tctx.moments(ft)[0, 1:]
-    diag = torch.zeros((total, 2 * binding.DIAG_LEN), dtype=torch.float64, device=dev)
-    fe = ectx.init_equilibrium(cuda(mem_uv))
     torch.cuda.synchronize()
     log(f"truth and {total} observation sets ready")
 
-    def cycle(c: int) -> None:
-        ectx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
+    def run_form(ctx):
+        """Warmup + timed cycles of one form; returns (elapsed s, diag, stage ms, counts)."""
+        diag = torch.zeros((total, 2 * binding.DIAG_LEN), dtype=torch.float64, device=dev)
+        fe = ctx.init_equilibrium(cuda(mem_uv))
+        for c in range(args.warmup):
+            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
+        torch.cuda.synchronize()
+        # timed region: per-launch HIP events on the launch stream
+        ctx.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(args.warmup, total):
+            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms, n = ctx.profile_collect()
+        ctx.set_profiling(False)
+        return el, diag[args.warmup:].cpu().numpy(), ms, n
 
-    # ---- warmup ---------------------------------------------------------------
-    for c in range(args.warmup):
-        cycle(c)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} cycles done")
+    elapsed, d, stage_ms, stage_n = run_form(ectx)
+    log(f"plain form: timed {args.steps} cycles in {elapsed:.3f} s")
+    forms = {}
+    if not args.no_forms:
+        f32ctx = binding.Context.from_config(cfg, force=force, route=route,
+                                             storage=binding.STORAGE_F32_DEV)
+        el32, d32, ms32, n32 = run_form(f32ctx)
+        log(f"precision form: timed {args.steps} cycles in {el32:.3f} s")
+        forms["f32_dev"] = {
+            "storage": "FP32 f - w, FP64 arithmetic",
+            "cycles_per_s": round(args.steps / el32, 3),
+            "speedup_vs_plain": round(elapsed / el32, 4),
+            "stream_collide_avg_us": round(1e3 * ms32[0] / max(n32[0], 1), 2),
+            "rmse_a_mean": float(d32[:, binding.DIAG_LEN].mean()),
+            "max_abs_rmse_a_diff_vs_plain": float(np.max(np.abs(
+                d32[:, binding.DIAG_LEN] - d[:, binding.DIAG_LEN]))),
+            "tolerance_1e-3_sigma": 1e-3 * cfg.sigma,
+        }
 
-    # ---- timed region: per-launch HIP events on the launch stream ----------
-    ectx.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for c in range(args.warmup, total):
-        cycle(c)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stage_ms, stage_n = ectx.profile_collect()
-    ectx.set_profiling(False)
-    log(f"timed {args.steps} cycles in {elapsed:.3f} s")
-
-    d = diag[args.warmup:].cpu().numpy()
     rmse_f, rmse_a = d[:, 0], d[:, binding.DIAG_LEN]
     nonfinite = float(d[:, 2].sum() + d[:, binding.DIAG_LEN + 2].sum())
     cycles_per_s = args.steps / elapsed
@@ -251,6 +267,8 @@ def main() -> int:
         "roofline": dominant,
         "roofline_other": other,
     }
+    if forms:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(cfg, force_np, pts, args.cpu_steps, args.cpu_nodes)

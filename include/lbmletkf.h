@@ -28,7 +28,7 @@
  * Lattice units: dx = dt = c = 1.  D2Q9 velocity order
  *   0:(0,0) 1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1) 5:(1,1) 6:(-1,-1) 7:(1,-1) 8:(-1,1).
  *
- * State layouts (FP64, members x 9 x ny x nx, x fastest):
+ * State layouts (members x 9 x ny x nx, x fastest; element type per lbmletkf_storage):
  *   canonical  f[m][a][y][x] = f_a(x, y) of member m, the pre-collision
  *              population of the lattice Boltzmann equation -- the state
  *              vector x(xi) = [f_0 .. f_8] the LETKF updates.
@@ -66,8 +66,12 @@ typedef enum {
     LBMLETKF_EUNSUPPORTED = -8 /* valid request this build does not implement */
 } lbmletkf_status;
 
-/* Storage precision of the populations. */
-typedef enum { LBMLETKF_F64 = 0 } lbmletkf_storage;
+/* Storage of the populations in every state buffer d_f:
+ *   F64      FP64 values f_a;
+ *   F32_DEV  FP32 deviations f_a - w_a from the lattice weights (the precision
+ *            form: half the bytes per step; all arithmetic stays FP64).
+ * Canonical buffers (import/export) are always FP64 values f_a. */
+typedef enum { LBMLETKF_F64 = 0, LBMLETKF_F32_DEV = 1 } lbmletkf_storage;
 
 /* Which eigenproblem the analysis solves (both give the same analysis):
  *   ENSEMBLE     the M x M matrix (M-1)/beta I + dY^T R_loc^-1 dY of Sec. 3.2.2;
@@ -122,26 +126,26 @@ lbmletkf_status lbmletkf_destroy(void* ctx);
 /* Equilibrium state f^eq(rho, u) (Sec. 2 equilibrium) in storage layout.
  * d_rho: [M][ny][nx] or NULL for rho = 1; d_uv: [M][2][ny][nx]. */
 lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const double* d_uv,
-                                          double* d_f, void* stream);
+                                          void* d_f, void* stream);
 
 /* canonical -> storage and storage -> canonical (buffers must not overlap). */
-lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, double* d_f, void* stream);
-lbmletkf_status lbmletkf_export(void* ctx, const double* d_f, double* d_canonical, void* stream);
+lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, void* d_f, void* stream);
+lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical, void* stream);
 
 /* a1 -- forecast (Sec. 2 LBE): advance every member nsteps >= 0 steps of
  * fused pull-stream + collide, in place on d_f (storage layout; the
  * workspace holds the ping-pong partner). */
-lbmletkf_status lbm_ensemble_step(void* ctx, double* d_f, int32_t nsteps, void* stream);
+lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* stream);
 
 /* a2 -- observation operator y = H x (Sec. 3): d_yf[M][nvar * n_points]. */
-lbmletkf_status observe(void* ctx, const double* d_f, double* d_yf, void* stream);
+lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream);
 
 /* a3..a8 -- LETKF analysis (Sec. 3.2.1, Sec. 3.2.2), in place on d_f:
  * ensemble statistics of d_yf against d_yo[nvar * n_points], then at every
  * node the localized ensemble-space problem, its symmetric
  * eigendecomposition, w_bar, dW = [(M-1) P~a]^(1/2) and
  * x_m^a = x_bar + dX (w_bar + dW[:, m]) applied to the nine populations. */
-lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const double* d_yo,
+lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
                               void* stream);
 
 /* a9 -- ensemble diagnostics into d_diag[LBMLETKF_DIAG_LEN]: RMSE of the
@@ -153,7 +157,7 @@ lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const 
 #define LBMLETKF_DIAG_NONFINITE 2
 #define LBMLETKF_DIAG_RHO_MIN 3
 #define LBMLETKF_DIAG_RHO_MAX 4
-lbmletkf_status lbmletkf_diagnostics(void* ctx, const double* d_f, const double* d_truth_uv,
+lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream);
 
 /* a10 -- one forecast-analysis cycle (Sec. 3 workflow (ii)-(iv)):
@@ -161,11 +165,11 @@ lbmletkf_status lbmletkf_diagnostics(void* ctx, const double* d_f, const double*
  * cycle's observations.  If d_diag is not NULL it receives the forecast
  * diagnostics in d_diag[0..7] and the analysis diagnostics in d_diag[8..15]
  * (d_truth_uv as in lbmletkf_diagnostics). */
-lbmletkf_status run_cycle(void* ctx, double* d_f, int32_t nsteps, const double* d_yo,
+lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_yo,
                           const double* d_truth_uv, double* d_diag, void* stream);
 
 /* rho, u, v of every node of every member: d_out[M][3][ny][nx]. */
-lbmletkf_status lbmletkf_moments(void* ctx, const double* d_f, double* d_out, void* stream);
+lbmletkf_status lbmletkf_moments(void* ctx, const void* d_f, double* d_out, void* stream);
 
 /* Synthetic observations y^o_q = y_q + sigma_q * eps_q for q < n (OSSE,
  * Sec. 4.3); all three arrays and d_yo are device [n]. */

@@ -23,6 +23,7 @@ DIAG_LEN = 8
 NSTAGES = 5
 STAGES = ("stream_collide", "observe", "obs_stats", "analysis", "diagnostics")
 ROUTE_AUTO, ROUTE_ENSEMBLE, ROUTE_OBSERVATION = 0, 1, 2
+STORAGE_F64, STORAGE_F32_DEV = 0, 1
 
 _c_int32 = ctypes.c_int32
 _c_double = ctypes.c_double
@@ -109,11 +110,12 @@ def _stream(stream=None) -> int:
     return stream.cuda_stream
 
 
-def _dev(t: Optional[torch.Tensor], numel: Optional[int] = None, name: str = "tensor"):
+def _dev(t: Optional[torch.Tensor], numel: Optional[int] = None, name: str = "tensor",
+         dtype=torch.float64):
     if t is None:
         return None
-    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
     return t.data_ptr()
@@ -123,18 +125,17 @@ def _dev(t: Optional[torch.Tensor], numel: Optional[int] = None, name: str = "te
 # C entry points under their own names
 # ---------------------------------------------------------------------------
 def lbm_ensemble_step(ctx: "Context", f: torch.Tensor, nsteps: int, stream=None) -> None:
-    _check(load().lbm_ensemble_step(ctx.handle, _dev(f, ctx.state_numel, "f"), int(nsteps),
-                                    _stream(stream)))
+    _check(load().lbm_ensemble_step(ctx.handle, ctx._state(f), int(nsteps), _stream(stream)))
 
 
 def observe(ctx: "Context", f: torch.Tensor, yf: torch.Tensor, stream=None) -> None:
-    _check(load().observe(ctx.handle, _dev(f, ctx.state_numel, "f"),
-                          _dev(yf, ctx.members * ctx.n_obs, "yf"), _stream(stream)))
+    _check(load().observe(ctx.handle, ctx._state(f), _dev(yf, ctx.members * ctx.n_obs, "yf"),
+                          _stream(stream)))
 
 
 def letkf_analyze(ctx: "Context", f: torch.Tensor, yf: torch.Tensor, yo: torch.Tensor,
                   stream=None) -> None:
-    _check(load().letkf_analyze(ctx.handle, _dev(f, ctx.state_numel, "f"),
+    _check(load().letkf_analyze(ctx.handle, ctx._state(f),
                                 _dev(yf, ctx.members * ctx.n_obs, "yf"),
                                 _dev(yo, ctx.n_obs, "yo"), _stream(stream)))
 
@@ -142,17 +143,17 @@ def letkf_analyze(ctx: "Context", f: torch.Tensor, yf: torch.Tensor, yo: torch.T
 def run_cycle(ctx: "Context", f: torch.Tensor, nsteps: int, yo: torch.Tensor,
               truth_uv: Optional[torch.Tensor] = None, diag: Optional[torch.Tensor] = None,
               stream=None) -> None:
-    _check(load().run_cycle(ctx.handle, _dev(f, ctx.state_numel, "f"), int(nsteps),
+    _check(load().run_cycle(ctx.handle, ctx._state(f), int(nsteps),
                             _dev(yo, ctx.n_obs, "yo"), _dev(truth_uv, 2 * ctx.plane, "truth_uv"),
                             _dev(diag, 2 * DIAG_LEN, "diag"), _stream(stream)))
 
 
 def plan(nx: int, ny: int, members: int, points, nvar: int, sigma: Sequence[float],
          d_cut: float, beta: float, tau0: float = 0.6, cs: float = 0.1, mu: float = 0.0,
-         route: int = ROUTE_AUTO) -> Tuple[int, int, int]:
+         route: int = ROUTE_AUTO, storage: int = STORAGE_F64) -> Tuple[int, int, int]:
     """Host-only: (max local points, eigenproblem size, route) -- no GPU needed."""
     lbm, obs, _keep = _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta,
-                              route)
+                              route, storage)
     a, b, c = _c_int32(), _c_int32(), _c_int32()
     _check(load().lbmletkf_plan(ctypes.byref(lbm), ctypes.byref(obs), ctypes.byref(a),
                                 ctypes.byref(b), ctypes.byref(c)))
@@ -161,18 +162,20 @@ def plan(nx: int, ny: int, members: int, points, nvar: int, sigma: Sequence[floa
 
 def workspace_bytes(nx: int, ny: int, members: int, points, nvar: int, sigma: Sequence[float],
                     d_cut: float, beta: float, tau0: float = 0.6, cs: float = 0.1,
-                    mu: float = 0.0, route: int = ROUTE_AUTO) -> int:
+                    mu: float = 0.0, route: int = ROUTE_AUTO, storage: int = STORAGE_F64) -> int:
     """Host-only: bytes of device workspace a context needs."""
     lbm, obs, _keep = _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta,
-                              route)
+                              route, storage)
     n = ctypes.c_size_t(0)
     _check(load().lbmletkf_workspace_bytes(ctypes.byref(lbm), ctypes.byref(obs), ctypes.byref(n)))
     return int(n.value)
 
 
-def _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta, route):
+def _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta, route,
+            storage=STORAGE_F64):
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 2))
-    lbm = LbmParams(int(nx), int(ny), int(members), float(tau0), float(cs), float(mu), 0)
+    lbm = LbmParams(int(nx), int(ny), int(members), float(tau0), float(cs), float(mu),
+                    int(storage))
     sig = list(sigma) + [1.0] * (3 - len(sigma))
     dc = float(d_cut) if math.isfinite(d_cut) else 0.0
     obs = ObsParams(len(pts), pts.ctypes.data_as(ctypes.POINTER(_c_int32)), int(nvar),
@@ -197,8 +200,10 @@ class Context:
     def __init__(self, nx: int, ny: int, members: int, tau0: float, cs: float,
                  points, nvar: int, sigma: Sequence[float], d_cut: float, beta: float,
                  mu: float = 0.0, force: Optional[torch.Tensor] = None,
-                 route: int = ROUTE_AUTO, device: str = "cuda"):
+                 route: int = ROUTE_AUTO, device: str = "cuda", storage: int = STORAGE_F64):
         lib = load()
+        self.storage = int(storage)
+        self.state_dtype = torch.float32 if self.storage == STORAGE_F32_DEV else torch.float64
         self.nx, self.ny, self.members, self.nvar = int(nx), int(ny), int(members), int(nvar)
         self.plane = self.nx * self.ny
         self.state_numel = self.members * 9 * self.plane
@@ -208,7 +213,7 @@ class Context:
         self.device = torch.device(device)
         self._lbm, self._obs, self.points = _params(self.nx, self.ny, self.members, tau0, cs, mu,
                                                     self.points, self.nvar, sigma, d_cut, beta,
-                                                    route)
+                                                    route, self.storage)
         nbytes = ctypes.c_size_t(0)
         _check(lib.lbmletkf_workspace_bytes(ctypes.byref(self._lbm), ctypes.byref(self._obs),
                                             ctypes.byref(nbytes)))
@@ -230,12 +235,16 @@ class Context:
     # -- construction from a configuration object (inputs.CycleConfig) --------
     @classmethod
     def from_config(cls, cfg, members: Optional[int] = None, force: Optional[torch.Tensor] = None,
-                    route: int = ROUTE_AUTO, points=None) -> "Context":
+                    route: int = ROUTE_AUTO, points=None,
+                    storage: int = STORAGE_F64) -> "Context":
         from . import inputs
         pts = inputs.observation_points(cfg) if points is None else points
         return cls(cfg.n, cfg.n, cfg.members if members is None else members, cfg.tau0, cfg.cs,
                    pts, cfg.nvar, cfg.sigmas, cfg.d_cut, cfg.beta, mu=cfg.mu, force=force,
-                   route=route)
+                   route=route, storage=storage)
+
+    def _state(self, f: torch.Tensor):
+        return _dev(f, self.state_numel, "f", self.state_dtype)
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and _lib is not None:
@@ -250,6 +259,10 @@ class Context:
 
     # -- buffers ---------------------------------------------------------------
     def new_state(self) -> torch.Tensor:
+        return torch.empty((self.members, 9, self.ny, self.nx), dtype=self.state_dtype,
+                           device=self.device)
+
+    def new_canonical(self) -> torch.Tensor:
         return torch.empty((self.members, 9, self.ny, self.nx), dtype=torch.float64,
                            device=self.device)
 
@@ -258,19 +271,18 @@ class Context:
         f = self.new_state()
         _check(load().lbmletkf_init_equilibrium(
             self.handle, _dev(rho, self.members * self.plane, "rho"),
-            _dev(uv, self.members * 2 * self.plane, "uv"), _dev(f), _stream(stream)))
+            _dev(uv, self.members * 2 * self.plane, "uv"), self._state(f), _stream(stream)))
         return f
 
     def import_canonical(self, canon: torch.Tensor, stream=None) -> torch.Tensor:
         f = self.new_state()
         _check(load().lbmletkf_import(self.handle, _dev(canon, self.state_numel, "canonical"),
-                                      _dev(f), _stream(stream)))
+                                      self._state(f), _stream(stream)))
         return f
 
     def export_canonical(self, f: torch.Tensor, stream=None) -> torch.Tensor:
-        out = self.new_state()
-        _check(load().lbmletkf_export(self.handle, _dev(f, self.state_numel, "f"), _dev(out),
-                                      _stream(stream)))
+        out = self.new_canonical()
+        _check(load().lbmletkf_export(self.handle, self._state(f), _dev(out), _stream(stream)))
         return out
 
     # -- the hot path ------------------------------------------------------------
@@ -296,7 +308,7 @@ class Context:
                     out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         if out is None:
             out = torch.empty(DIAG_LEN, dtype=torch.float64, device=self.device)
-        _check(load().lbmletkf_diagnostics(self.handle, _dev(f, self.state_numel, "f"),
+        _check(load().lbmletkf_diagnostics(self.handle, self._state(f),
                                            _dev(truth_uv, 2 * self.plane, "truth_uv"),
                                            _dev(out, DIAG_LEN, "diag"), _stream(stream)))
         return out
@@ -304,8 +316,7 @@ class Context:
     def moments(self, f: torch.Tensor, stream=None) -> torch.Tensor:
         out = torch.empty((self.members, 3, self.ny, self.nx), dtype=torch.float64,
                           device=self.device)
-        _check(load().lbmletkf_moments(self.handle, _dev(f, self.state_numel, "f"), _dev(out),
-                                       _stream(stream)))
+        _check(load().lbmletkf_moments(self.handle, self._state(f), _dev(out), _stream(stream)))
         return out
 
     def local_histogram(self) -> np.ndarray:

@@ -69,7 +69,11 @@ struct Ctx {
     };
     std::vector<Rec> recs;
 
-    double* fbuf() const { return reinterpret_cast<double*>(ws + L.fbuf); }
+    void* fbuf() const { return ws + L.fbuf; }
+    int storage() const { return lbm.storage; }
+    size_t state_bytes() const {
+        return (size_t)dims.nx * dims.ny * 9 * dims.members * state_elem_bytes(lbm.storage);
+    }
     const double* force() const {
         return has_force ? reinterpret_cast<const double*>(ws + L.force) : nullptr;
     }
@@ -118,8 +122,8 @@ lbmletkf_status check_lbm(const lbmletkf_lbm_params* p) {
         return fail(LBMLETKF_EINVAL, "tau0 must be finite and > 1/2");
     if (!(p->cs >= 0.0) || !std::isfinite(p->cs)) return fail(LBMLETKF_EINVAL, "cs must be >= 0");
     if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return fail(LBMLETKF_EINVAL, "mu must be >= 0");
-    if (p->storage != LBMLETKF_F64)
-        return fail(LBMLETKF_EUNSUPPORTED, "only FP64 storage is implemented");
+    if (p->storage != LBMLETKF_F64 && p->storage != LBMLETKF_F32_DEV)
+        return fail(LBMLETKF_EINVAL, "storage must be LBMLETKF_F64 or LBMLETKF_F32_DEV");
     return LBMLETKF_OK;
 }
 
@@ -210,7 +214,7 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
         off = align_up(off + bytes);
         return at;
     };
-    L.fbuf = take(plane * 9 * p->members * sizeof(double));
+    L.fbuf = take(plane * 9 * p->members * state_elem_bytes(p->storage));
     L.force = take(plane * 2 * sizeof(double));
     L.loc_pt = take(plane * std::max(lmax, 1) * sizeof(int));
     L.loc_g = take(plane * std::max(lmax, 1) * sizeof(double));
@@ -392,63 +396,62 @@ lbmletkf_status lbmletkf_destroy(void* ctx) {
 }
 
 lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const double* d_uv,
-                                          double* d_f, void* stream) {
+                                          void* d_f, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_uv || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
-    hipError_t e = launch_init_equilibrium(d_rho, d_uv, d_f, c->dims, as_stream(stream));
+    hipError_t e = launch_init_equilibrium(d_rho, d_uv, d_f, c->dims, c->storage(), as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "init_equilibrium");
 }
 
-lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, double* d_f, void* stream) {
+lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, void* d_f, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_canonical || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
     if ((const void*)d_canonical == (const void*)d_f)
         return fail(LBMLETKF_EINVAL, "import cannot run in place");
-    hipError_t e = launch_import(d_canonical, d_f, c->dims, as_stream(stream));
+    hipError_t e = launch_import(d_canonical, d_f, c->dims, c->storage(), as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "import");
 }
 
-lbmletkf_status lbmletkf_export(void* ctx, const double* d_f, double* d_canonical, void* stream) {
+lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_canonical || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
     if ((const void*)d_canonical == (const void*)d_f)
         return fail(LBMLETKF_EINVAL, "export cannot run in place");
-    hipError_t e = launch_export(d_f, d_canonical, c->dims, as_stream(stream));
+    hipError_t e = launch_export(d_f, d_canonical, c->dims, c->storage(), as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "export");
 }
 
-lbmletkf_status lbm_ensemble_step(void* ctx, double* d_f, int32_t nsteps, void* stream) {
+lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(LBMLETKF_EINVAL, "nsteps must be >= 0");
     hipStream_t s = as_stream(stream);
-    double* a = d_f;
-    double* b = c->fbuf();
+    void* a = d_f;
+    void* b = c->fbuf();
     for (int k = 0; k < nsteps; ++k) {
         StageTimer t(c, kStageCollide, s);
         hipError_t e = launch_stream_collide(a, b, c->force(), c->dims, c->lbm.tau0, c->lbm.cs,
-                                             c->lbm.mu, s);
+                                             c->lbm.mu, c->storage(), s);
         if (e != hipSuccess) return hip_fail(e, "stream_collide");
         std::swap(a, b);
     }
     if (a != d_f) {
-        const size_t bytes = (size_t)c->dims.nx * c->dims.ny * 9 * c->dims.members * sizeof(double);
-        hipError_t e = hipMemcpyAsync(d_f, a, bytes, hipMemcpyDeviceToDevice, s);
+        hipError_t e = hipMemcpyAsync(d_f, a, c->state_bytes(), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "ping-pong copy");
     }
     return LBMLETKF_OK;
 }
 
-lbmletkf_status observe(void* ctx, const double* d_f, double* d_yf, void* stream) {
+lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yf) return fail(LBMLETKF_EINVAL, "NULL argument");
     StageTimer t(c, kStageObserve, as_stream(stream));
     hipError_t e = launch_observe(d_f, c->pts(), c->obs.n_points, c->obs.nvar, d_yf, c->dims,
-                                  as_stream(stream));
+                                  c->storage(), as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "observe");
 }
 
-lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const double* d_yo,
+lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
                               void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yf || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
@@ -462,6 +465,7 @@ lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const 
     }
     AnalysisParams p{};
     p.f = d_f;
+    p.storage = c->storage();
     p.nx = c->dims.nx;
     p.ny = c->dims.ny;
     p.members = c->dims.members;
@@ -502,18 +506,18 @@ lbmletkf_status letkf_analyze(void* ctx, double* d_f, const double* d_yf, const 
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "analysis");
 }
 
-lbmletkf_status lbmletkf_diagnostics(void* ctx, const double* d_f, const double* d_truth_uv,
+lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_diag) return fail(LBMLETKF_EINVAL, "NULL argument");
     StageTimer t(c, kStageDiag, as_stream(stream));
-    hipError_t e = launch_diag(d_f, d_truth_uv, c->dims, c->partial(),
+    hipError_t e = launch_diag(d_f, d_truth_uv, c->dims, c->storage(), c->partial(),
                                diag_blocks_for(c->dims.nx * c->dims.ny), d_diag,
                                as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
 }
 
-lbmletkf_status run_cycle(void* ctx, double* d_f, int32_t nsteps, const double* d_yo,
+lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_yo,
                           const double* d_truth_uv, double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
@@ -528,10 +532,10 @@ lbmletkf_status run_cycle(void* ctx, double* d_f, int32_t nsteps, const double* 
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_moments(void* ctx, const double* d_f, double* d_out, void* stream) {
+lbmletkf_status lbmletkf_moments(void* ctx, const void* d_f, double* d_out, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_out) return fail(LBMLETKF_EINVAL, "NULL argument");
-    hipError_t e = launch_moments(d_f, d_out, c->dims, as_stream(stream));
+    hipError_t e = launch_moments(d_f, d_out, c->dims, c->storage(), as_stream(stream));
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "moments");
 }
 

@@ -23,6 +23,36 @@ __host__ __device__ constexpr double w_of(int a) {
 
 constexpr int kWave = 64;
 
+// Population storage: FP64 values f, or FP32 deviations f - w from the lattice
+// weights (the precision form).  Arithmetic is FP64 in both cases; only the
+// bytes kept in HBM differ.
+enum Storage { kStoreF64 = 0, kStoreF32Dev = 1 };
+
+template <typename T>
+struct PopIO;
+
+template <>
+struct PopIO<double> {
+    __device__ static double load(const double* p, int) { return *p; }
+    __device__ static double load_nt(const double* p, int) { return __builtin_nontemporal_load(p); }
+    __device__ static void store(double* p, int, double v) { *p = v; }
+    __device__ static void store_nt(double* p, int, double v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct PopIO<float> {
+    __device__ static double load(const float* p, int a) { return w_of(a) + (double)*p; }
+    __device__ static double load_nt(const float* p, int a) {
+        return w_of(a) + (double)__builtin_nontemporal_load(p);
+    }
+    __device__ static void store(float* p, int a, double v) { *p = (float)(v - w_of(a)); }
+    __device__ static void store_nt(float* p, int a, double v) {
+        __builtin_nontemporal_store((float)(v - w_of(a)), p);
+    }
+};
+
+inline size_t state_elem_bytes(int storage) { return storage == kStoreF32Dev ? 4 : 8; }
+
 // Stage identifiers for per-launch timing.
 enum Stage { kStageCollide = 0, kStageObserve = 1, kStageStats = 2, kStageAnalysis = 3,
              kStageDiag = 4, kNumStages = 5 };
@@ -33,24 +63,26 @@ struct LbmDims {
 
 // ---- lattice-Boltzmann kernels (lbm_kernels.hip) -------------------------
 // One fused pull-stream + BGK-Smagorinsky collide step, fin -> fout (storage layout).
-hipError_t launch_stream_collide(const double* fin, double* fout, const double* force,
-                                 LbmDims d, double tau0, double cs, double mu, hipStream_t s);
-hipError_t launch_import(const double* canon, double* f, LbmDims d, hipStream_t s);
-hipError_t launch_export(const double* f, double* canon, LbmDims d, hipStream_t s);
-hipError_t launch_init_equilibrium(const double* rho, const double* uv, double* f, LbmDims d,
-                                   hipStream_t s);
-hipError_t launch_moments(const double* f, double* out, LbmDims d, hipStream_t s);
+// `storage` selects the element type of every state buffer (Storage).
+hipError_t launch_stream_collide(const void* fin, void* fout, const double* force, LbmDims d,
+                                 double tau0, double cs, double mu, int storage, hipStream_t s);
+hipError_t launch_import(const double* canon, void* f, LbmDims d, int storage, hipStream_t s);
+hipError_t launch_export(const void* f, double* canon, LbmDims d, int storage, hipStream_t s);
+hipError_t launch_init_equilibrium(const double* rho, const double* uv, void* f, LbmDims d,
+                                   int storage, hipStream_t s);
+hipError_t launch_moments(const void* f, double* out, LbmDims d, int storage, hipStream_t s);
 
 // ---- observation, statistics, analysis, diagnostics (letkf_kernels.hip) ---
-hipError_t launch_observe(const double* f, const int* pts, int npts, int nvar, double* yf,
-                          LbmDims d, hipStream_t s);
+hipError_t launch_observe(const void* f, const int* pts, int npts, int nvar, double* yf,
+                          LbmDims d, int storage, hipStream_t s);
 hipError_t launch_obs_stats(const double* yf, const double* yo, int nobs, int members,
                             double* ybar, double* dY, double* dvec, double* K, hipStream_t s);
 hipError_t launch_local_table(const int* pts, int npts, double d_cut, int lmax, int nx, int ny,
                               int* loc_pt, double* loc_g, int* overflow, hipStream_t s);
 
 struct AnalysisParams {
-    double* f;            // storage layout [M][9][ny][nx], updated in place
+    void* f;              // storage layout [M][9][ny][nx], updated in place
+    int storage;          // Storage of f
     int nx, ny, members;
     const double* dY;     // [nobs][M] forecast observation perturbations
     const double* K;      // [nobs][nobs] = dY dY^T (observation route)
@@ -74,8 +106,8 @@ int obs_size_for(int n);              // instantiated size >= n, or 0
 int obs_lds_bytes(int n);
 int diag_blocks_for(int plane);
 
-hipError_t launch_diag(const double* f, const double* truth_uv, LbmDims d, double* partial,
-                       int nblocks, double* out, hipStream_t s);
+hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int storage,
+                       double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_synth_obs(const double* y, const double* eps, const double* sigma, double* yo,
                             int n, hipStream_t s);
 

@@ -55,9 +55,10 @@ __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
-    const double* __restrict__ fin, double* __restrict__ fout, const double* __restrict__ force,
-    int nx, int ny, double tau0, double smag, double mu) {
+    const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
+    int ny, double tau0, double smag, double mu) {
     const int plane = nx * ny;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= plane) return;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
     const int y = i / nx, x = i - y * nx;
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-    const double* __restrict__ b = fin + (size_t)m * 9 * plane;
+    const T* __restrict__ b = fin + (size_t)m * 9 * plane;
     const int rc = y * nx, rm = ym * nx, rp = yp * nx;
     // every population is read once and written once per step: stream it
     // past the caches (nontemporal loads and stores)
@@ -80,20 +81,21 @@ __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
                            (size_t)8 * plane + rm + xp};
     double f[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = __builtin_nontemporal_load(b + src[a]);
+    for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(b + src[a], a);
     double fx = 0.0, fy = 0.0;
     if (force) {
         fx = force[i];
         fy = force[plane + i];
     }
     collide_node(f, tau0, smag, fx, fy, mu);
-    double* __restrict__ o = fout + (size_t)m * 9 * plane + i;
+    T* __restrict__ o = fout + (size_t)m * 9 * plane + i;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) __builtin_nontemporal_store(f[a], o + (size_t)a * plane);
+    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(o + (size_t)a * plane, a, f[a]);
 }
 
 // storage slot (a, y, x) <- canonical (a, y + c_ay, x + c_ax)
-__global__ void import_kernel(const double* __restrict__ canon, double* __restrict__ f, int nx,
+template <typename T>
+__global__ void import_kernel(const double* __restrict__ canon, T* __restrict__ f, int nx,
                               int ny, int members) {
     const size_t plane = (size_t)nx * ny;
     const size_t total = plane * 9 * members;
@@ -103,12 +105,13 @@ __global__ void import_kernel(const double* __restrict__ canon, double* __restri
         const int a = (int)((t / plane) % 9);
         const int y = (int)(i / nx), x = (int)(i % nx);
         const int xs = (x + cx_of(a) + nx) % nx, ys = (y + cy_of(a) + ny) % ny;
-        f[t] = canon[t - i + (size_t)ys * nx + xs];
+        PopIO<T>::store(f + t, a, canon[t - i + (size_t)ys * nx + xs]);
     }
 }
 
 // canonical (a, y, x) <- storage slot (a, y - c_ay, x - c_ax)
-__global__ void export_kernel(const double* __restrict__ f, double* __restrict__ canon, int nx,
+template <typename T>
+__global__ void export_kernel(const T* __restrict__ f, double* __restrict__ canon, int nx,
                               int ny, int members) {
     const size_t plane = (size_t)nx * ny;
     const size_t total = plane * 9 * members;
@@ -118,14 +121,15 @@ __global__ void export_kernel(const double* __restrict__ f, double* __restrict__
         const int a = (int)((t / plane) % 9);
         const int y = (int)(i / nx), x = (int)(i % nx);
         const int xs = (x - cx_of(a) + nx) % nx, ys = (y - cy_of(a) + ny) % ny;
-        canon[t] = f[t - i + (size_t)ys * nx + xs];
+        canon[t] = PopIO<T>::load(f + (t - i + (size_t)ys * nx + xs), a);
     }
 }
 
 // f^eq(rho, u) written to the storage slots of node (x, y).
+template <typename T>
 __global__ void init_equilibrium_kernel(const double* __restrict__ rho_in,
-                                        const double* __restrict__ uv, double* __restrict__ f,
-                                        int nx, int ny, int members) {
+                                        const double* __restrict__ uv, T* __restrict__ f, int nx,
+                                        int ny, int members) {
     const size_t plane = (size_t)nx * ny;
     const size_t total = plane * members;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
@@ -140,14 +144,15 @@ __global__ void init_equilibrium_kernel(const double* __restrict__ rho_in,
         for (int a = 0; a < 9; ++a) {
             const double cu = cx_of(a) * u + cy_of(a) * v;
             const int xs = (x - cx_of(a) + nx) % nx, ys = (y - cy_of(a) + ny) % ny;
-            f[(m * 9 + a) * plane + (size_t)ys * nx + xs] =
-                rho * w_of(a) * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
+            PopIO<T>::store(f + ((m * 9 + a) * plane + (size_t)ys * nx + xs), a,
+                            rho * w_of(a) * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq));
         }
     }
 }
 
 // rho, u, v of every node from the canonical populations.
-__global__ void moments_kernel(const double* __restrict__ f, double* __restrict__ out, int nx,
+template <typename T>
+__global__ void moments_kernel(const T* __restrict__ f, double* __restrict__ out, int nx,
                                int ny, int members) {
     const size_t plane = (size_t)nx * ny;
     const size_t total = plane * members;
@@ -160,7 +165,7 @@ __global__ void moments_kernel(const double* __restrict__ f, double* __restrict_
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const int xs = (x - cx_of(a) + nx) % nx, ys = (y - cy_of(a) + ny) % ny;
-            const double fa = f[(m * 9 + a) * plane + (size_t)ys * nx + xs];
+            const double fa = PopIO<T>::load(f + ((m * 9 + a) * plane + (size_t)ys * nx + xs), a);
             rho += fa;
             jx += cx_of(a) * fa;
             jy += cy_of(a) * fa;
@@ -178,38 +183,62 @@ int grid_for(size_t total, int block) {
 
 }  // namespace
 
-hipError_t launch_stream_collide(const double* fin, double* fout, const double* force, LbmDims d,
-                                 double tau0, double cs, double mu, hipStream_t s) {
+hipError_t launch_stream_collide(const void* fin, void* fout, const double* force, LbmDims d,
+                                 double tau0, double cs, double mu, int storage, hipStream_t s) {
     const int plane = d.nx * d.ny;
     dim3 grid((plane + kBlock - 1) / kBlock, d.members);
     const double smag = 18.0 * sqrt(2.0) * cs * cs;
-    stream_collide_kernel<<<grid, kBlock, 0, s>>>(fin, fout, force, d.nx, d.ny, tau0, smag, mu);
+    if (storage == kStoreF32Dev)
+        stream_collide_kernel<float><<<grid, kBlock, 0, s>>>(
+            (const float*)fin, (float*)fout, force, d.nx, d.ny, tau0, smag, mu);
+    else
+        stream_collide_kernel<double><<<grid, kBlock, 0, s>>>(
+            (const double*)fin, (double*)fout, force, d.nx, d.ny, tau0, smag, mu);
     return hipGetLastError();
 }
 
-hipError_t launch_import(const double* canon, double* f, LbmDims d, hipStream_t s) {
+hipError_t launch_import(const double* canon, void* f, LbmDims d, int storage, hipStream_t s) {
     size_t total = (size_t)d.nx * d.ny * 9 * d.members;
-    import_kernel<<<grid_for(total, 256), 256, 0, s>>>(canon, f, d.nx, d.ny, d.members);
+    if (storage == kStoreF32Dev)
+        import_kernel<float><<<grid_for(total, 256), 256, 0, s>>>(canon, (float*)f, d.nx, d.ny,
+                                                                  d.members);
+    else
+        import_kernel<double><<<grid_for(total, 256), 256, 0, s>>>(canon, (double*)f, d.nx, d.ny,
+                                                                   d.members);
     return hipGetLastError();
 }
 
-hipError_t launch_export(const double* f, double* canon, LbmDims d, hipStream_t s) {
+hipError_t launch_export(const void* f, double* canon, LbmDims d, int storage, hipStream_t s) {
     size_t total = (size_t)d.nx * d.ny * 9 * d.members;
-    export_kernel<<<grid_for(total, 256), 256, 0, s>>>(f, canon, d.nx, d.ny, d.members);
+    if (storage == kStoreF32Dev)
+        export_kernel<float><<<grid_for(total, 256), 256, 0, s>>>((const float*)f, canon, d.nx,
+                                                                  d.ny, d.members);
+    else
+        export_kernel<double><<<grid_for(total, 256), 256, 0, s>>>((const double*)f, canon, d.nx,
+                                                                   d.ny, d.members);
     return hipGetLastError();
 }
 
-hipError_t launch_init_equilibrium(const double* rho, const double* uv, double* f, LbmDims d,
-                                   hipStream_t s) {
+hipError_t launch_init_equilibrium(const double* rho, const double* uv, void* f, LbmDims d,
+                                   int storage, hipStream_t s) {
     size_t total = (size_t)d.nx * d.ny * d.members;
-    init_equilibrium_kernel<<<grid_for(total, 256), 256, 0, s>>>(rho, uv, f, d.nx, d.ny,
-                                                                 d.members);
+    if (storage == kStoreF32Dev)
+        init_equilibrium_kernel<float><<<grid_for(total, 256), 256, 0, s>>>(
+            rho, uv, (float*)f, d.nx, d.ny, d.members);
+    else
+        init_equilibrium_kernel<double><<<grid_for(total, 256), 256, 0, s>>>(
+            rho, uv, (double*)f, d.nx, d.ny, d.members);
     return hipGetLastError();
 }
 
-hipError_t launch_moments(const double* f, double* out, LbmDims d, hipStream_t s) {
+hipError_t launch_moments(const void* f, double* out, LbmDims d, int storage, hipStream_t s) {
     size_t total = (size_t)d.nx * d.ny * d.members;
-    moments_kernel<<<grid_for(total, 256), 256, 0, s>>>(f, out, d.nx, d.ny, d.members);
+    if (storage == kStoreF32Dev)
+        moments_kernel<float><<<grid_for(total, 256), 256, 0, s>>>((const float*)f, out, d.nx,
+                                                                   d.ny, d.members);
+    else
+        moments_kernel<double><<<grid_for(total, 256), 256, 0, s>>>((const double*)f, out, d.nx,
+                                                                    d.ny, d.members);
     return hipGetLastError();
 }
 

@@ -31,9 +31,9 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // observation operator: yf[m][nvar*k + var]
 // ---------------------------------------------------------------------------
-__global__ void observe_kernel(const double* __restrict__ f, const int* __restrict__ pts,
-                               int npts, int nvar, double* __restrict__ yf, int nx, int ny,
-                               int members) {
+template <typename T>
+__global__ void observe_kernel(const T* __restrict__ f, const int* __restrict__ pts, int npts,
+                               int nvar, double* __restrict__ yf, int nx, int ny, int members) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts * members) return;
     const int m = t / npts, k = t - m * npts;
@@ -43,7 +43,7 @@ __global__ void observe_kernel(const double* __restrict__ f, const int* __restri
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-        const double fa = f[((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs];
+        const double fa = PopIO<T>::load(f + (((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs), a);
         rho += fa;
         jx += cx_of(a) * fa;
         jy += cy_of(a) * fa;
@@ -139,8 +139,9 @@ __host__ __device__ inline int ens_lds_doubles(int n, int nz) {
     return 9 * 64 + n * rs + 4 * 64 + 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
 }
 
-template <int N>
+template <int N, typename T>
 __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int max_sweeps) {
+    T* __restrict__ fs = reinterpret_cast<T*>(p.f);
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int nx = p.nx, ny = p.ny, M = p.members;
@@ -167,7 +168,8 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-        fv[a] = mem ? p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs] : 0.0;
+        fv[a] = mem ? PopIO<T>::load(fs + (((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs), a)
+                    : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -242,7 +244,8 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
 #pragma unroll
             for (int c = 0; c < N; ++c) acc += se[a * N + c] * U[c];
             const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs] = xbar[a] + dmean[a] + acc;
+            PopIO<T>::store(fs + (((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs), a,
+                            xbar[a] + dmean[a] + acc);
         }
     }
 }
@@ -255,9 +258,10 @@ constexpr int kDiagBlock = 256;
 constexpr int kDiagNodes = 64;  // nodes per block; 4 member groups per node
 constexpr int kDiagFields = 5;  // err2, spread2, nonfinite, rho_min, rho_max
 
+template <typename T>
 __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
-    const double* __restrict__ f, const double* __restrict__ truth_uv, int nx, int ny,
-    int members, double* __restrict__ partial) {
+    const T* __restrict__ f, const double* __restrict__ truth_uv, int nx, int ny, int members,
+    double* __restrict__ partial) {
     const int plane = nx * ny;
     const int tx = threadIdx.x & (kDiagNodes - 1);
     const int g = threadIdx.x / kDiagNodes;  // member group 0..3
@@ -270,7 +274,8 @@ __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-                const double fa = f[((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs];
+                const double fa =
+                    PopIO<T>::load(f + (((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs), a);
                 rho += fa;
                 jx += cx_of(a) * fa;
                 jy += cy_of(a) * fa;
@@ -384,18 +389,23 @@ __global__ void synth_obs_kernel(const double* __restrict__ y, const double* __r
     if (q < n) yo[q] = y[q] + sigma[q] * eps[q];
 }
 
-template <int N>
-hipError_t launch_ens(const AnalysisParams& p, hipStream_t s) {
+template <int N, typename T>
+hipError_t launch_ens_t(const AnalysisParams& p, hipStream_t s) {
     const size_t bytes = (size_t)ens_lds_doubles(N, p.nvar * p.lmax) * sizeof(double);
     const int plane = p.nx * p.ny;
     if (bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)analysis_ens_kernel<N>,
+        hipError_t e = hipFuncSetAttribute((const void*)analysis_ens_kernel<N, T>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)bytes);
         if (e != hipSuccess) return e;
     }
-    analysis_ens_kernel<N><<<plane, 64, bytes, s>>>(p, 30);
+    analysis_ens_kernel<N, T><<<plane, 64, bytes, s>>>(p, 30);
     return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_ens(const AnalysisParams& p, hipStream_t s) {
+    return p.storage == kStoreF32Dev ? launch_ens_t<N, float>(p, s) : launch_ens_t<N, double>(p, s);
 }
 
 hipError_t launch_ens_sized(const AnalysisParams& p, int n, hipStream_t s) {
@@ -421,11 +431,15 @@ int ens_size_for(int n) {
 
 int ens_lds_bytes(int n, int nz) { return ens_lds_doubles(n, nz) * (int)sizeof(double); }
 
-hipError_t launch_observe(const double* f, const int* pts, int npts, int nvar, double* yf,
-                          LbmDims d, hipStream_t s) {
+hipError_t launch_observe(const void* f, const int* pts, int npts, int nvar, double* yf,
+                          LbmDims d, int storage, hipStream_t s) {
     const int total = npts * d.members;
-    observe_kernel<<<(total + 255) / 256, 256, 0, s>>>(f, pts, npts, nvar, yf, d.nx, d.ny,
-                                                        d.members);
+    if (storage == kStoreF32Dev)
+        observe_kernel<float><<<(total + 255) / 256, 256, 0, s>>>((const float*)f, pts, npts, nvar,
+                                                                   yf, d.nx, d.ny, d.members);
+    else
+        observe_kernel<double><<<(total + 255) / 256, 256, 0, s>>>((const double*)f, pts, npts,
+                                                                    nvar, yf, d.nx, d.ny, d.members);
     return hipGetLastError();
 }
 
@@ -453,11 +467,16 @@ hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s) {
 
 int diag_blocks_for(int plane) { return (plane + kDiagNodes - 1) / kDiagNodes; }
 
-hipError_t launch_diag(const double* f, const double* truth_uv, LbmDims d, double* partial,
-                       int nblocks, double* out, hipStream_t s) {
+hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int storage,
+                       double* partial, int nblocks, double* out, hipStream_t s) {
     const int need = diag_blocks_for(d.nx * d.ny);
     if (need > nblocks) return hipErrorInvalidValue;
-    diag_partial_kernel<<<need, kDiagBlock, 0, s>>>(f, truth_uv, d.nx, d.ny, d.members, partial);
+    if (storage == kStoreF32Dev)
+        diag_partial_kernel<float><<<need, kDiagBlock, 0, s>>>((const float*)f, truth_uv, d.nx, d.ny,
+                                                               d.members, partial);
+    else
+        diag_partial_kernel<double><<<need, kDiagBlock, 0, s>>>((const double*)f, truth_uv, d.nx,
+                                                                d.ny, d.members, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     diag_final_kernel<<<1, kDiagBlock, 0, s>>>(partial, need, d.nx * d.ny, out);

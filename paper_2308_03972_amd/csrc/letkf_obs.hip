@@ -40,9 +40,10 @@ struct ObsLayout {
     static constexpr int total = kRows + kBC + kVec + kObs + kXbar;
 };
 
-template <int N>
+template <int N, typename T>
 __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, const int* nodes,
                                                           int count, int max_sweeps) {
+    T* __restrict__ fs = reinterpret_cast<T*>(p.f);
     using L = ObsLayout<N>;
     constexpr int SEGS = L::SEGS;
     extern __shared__ double lds[];
@@ -83,8 +84,9 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            dx[a] = (valid && mem) ? p.f[((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs]
-                                   : 0.0;
+            dx[a] = (valid && mem)
+                        ? PopIO<T>::load(fs + (((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs), a)
+                        : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
@@ -271,10 +273,10 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-                double* slot = p.f + ((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs;
-                const double fa = *slot;
+                T* slot = fs + ((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs;
+                const double fa = PopIO<T>::load(slot, a);
                 const double xbar = xb[sg * 9 + a];
-                *slot = xbar + p.sqrt_beta * (fa - xbar) + dmv[sg * 9 + a] + acc[a];
+                PopIO<T>::store(slot, a, xbar + p.sqrt_beta * (fa - xbar) + dmv[sg * 9 + a] + acc[a]);
             }
         }
     }
@@ -286,7 +288,10 @@ hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, hipStr
     const size_t bytes = (size_t)L::total * sizeof(double);
     const int blocks = (count + L::SEGS - 1) / L::SEGS;
     if (blocks == 0) return hipSuccess;
-    analysis_obs_kernel<N><<<blocks, 64, bytes, s>>>(p, nodes, count, 30);
+    if (p.storage == kStoreF32Dev)
+        analysis_obs_kernel<N, float><<<blocks, 64, bytes, s>>>(p, nodes, count, 30);
+    else
+        analysis_obs_kernel<N, double><<<blocks, 64, bytes, s>>>(p, nodes, count, 30);
     return hipGetLastError();
 }
 
