@@ -24,7 +24,12 @@ Readings of points the paper leaves open (all are explicit config fields):
 * members = truth + an independent field of the same spectrum at
   ``member_amp`` * urms;
 * steady body force F = (A sin(2 pi k y / n), 0) at k = 4, with A chosen so
-  that the laminar Kolmogorov flow it drives has rms velocity urms;
+  that the laminar Kolmogorov flow it drives has rms velocity urms; or, for the
+  paper's own physics, the shell forcing of Sec. 4.1, F = dx grad(F_e) x i_z,
+  F_e = sum over the integer wavevectors with ||k| - k_f| <= dk of
+  r1.k cos(k.xi) + r2.k sin(k.xi) with Gaussian random vectors r1, r2 per
+  wavevector, drawn once (steady), and F_e0 fixed by the reading that the force
+  has the same rms as the sinusoidal force;
 * observation points on a uniform lattice (a*p, b*p), p = n / obs_side,
   point index k = b*obs_side + a, observation index q = nvar*k + var,
   var = (u, v) for nvar = 2 and (rho, u, v) for nvar = 3 (eq. for y, Sec. 3);
@@ -66,6 +71,8 @@ class CycleConfig:
     urms: float = 0.05 * math.sqrt(CS2)
     member_amp: float = 0.2
     nvar: int = 2               # 2: (u, v); 3: (rho, u, v)
+    forcing: str = "kolmogorov"  # "kolmogorov" (sinusoidal) or "shell" (Sec. 4.1)
+    shell_width: float = 2.0    # dk of the shell forcing
     sigma_uv: Optional[float] = None    # None: 0.1 * urms
     sigma_rho: float = 0.01
     seed: int = SEED
@@ -125,6 +132,15 @@ CONFIGS: Dict[str, CycleConfig] = {
     "precision": CycleConfig(name="precision", n=512, members=64, tau0=0.52,
                              cs=0.1, obs_side=16, loc_r=16.0,
                              steps_per_cycle=20, cycles=100),
+    # The paper's own physics (Sec. 4.1, Table 1, Sec. 4.3) on 256^2: nu = 1e-4,
+    # dt = 0.001232, dx = 2 pi / 256 give tau0 = 1/2 + 3 nu dt / dx^2; C_s = 0.2;
+    # friction mu dt per step; shell forcing k_f = 4, dk = 2; (rho, u, v)
+    # observed every p = 32 cells; d_cut = p (so r = p / sqrt 3); s = 200.
+    "paper_physics": CycleConfig(
+        name="paper_physics", n=256, members=64,
+        tau0=0.5 + 3.0 * 1e-4 * 0.001232 / (2.0 * math.pi / 256) ** 2, cs=0.2,
+        obs_side=8, loc_r=32.0 / math.sqrt(3.0), steps_per_cycle=200, cycles=20,
+        mu=5e-4 * 0.001232, nvar=3, forcing="shell"),
 }
 
 
@@ -138,8 +154,9 @@ def streams(cfg: CycleConfig, cycles: Optional[int] = None) -> Dict[str, object]
     the configuration holds leaves the first ones unchanged."""
     n_noise = max(cfg.cycles, cycles or 0) + 1
     root = np.random.SeedSequence(cfg.seed)
-    truth_ss, member_ss, noise_ss = root.spawn(3)
+    truth_ss, member_ss, noise_ss, force_ss = root.spawn(4)
     return {
+        "force": np.random.Generator(np.random.PCG64(force_ss)),
         "truth": np.random.Generator(np.random.PCG64(truth_ss)),
         "members": [np.random.Generator(np.random.PCG64(s))
                     for s in member_ss.spawn(cfg.members)],
@@ -192,11 +209,47 @@ def initial_velocities(cfg: CycleConfig) -> Tuple[np.ndarray, np.ndarray]:
 
 def body_force(cfg: CycleConfig) -> np.ndarray:
     """Steady acceleration field [2][n][n] = (Fx, Fy), index [.][y][x]."""
+    if cfg.forcing == "shell":
+        return shell_force(cfg)
     y = np.arange(cfg.n, dtype=np.float64)
     fx_row = cfg.amplitude * np.sin(2.0 * np.pi * cfg.force_k * y / cfg.n)
     force = np.zeros((2, cfg.n, cfg.n))
     force[0] = fx_row[:, None]
     return force
+
+
+def shell_force(cfg: CycleConfig) -> np.ndarray:
+    """Divergence-free random shell forcing (Sec. 4.1), [2][n][n].
+
+    F_e(xi) = sum_k r1_k.k cos(k.xi) + r2_k.k sin(k.xi) over integer wavevectors
+    with ||k| - k_f| <= dk on the 2 pi periodic box (xi = 2 pi (x, y) / n),
+    r1_k, r2_k independent standard-normal 2-vectors; F = (dF_e/dy, -dF_e/dx),
+    scaled to rms sqrt(<Fx^2 + Fy^2>) = A / sqrt 2 (the sinusoidal force's rms).
+    """
+    rng = streams(cfg)["force"]
+    n = cfg.n
+    xi = 2.0 * np.pi * np.arange(n) / n
+    X, Y = np.meshgrid(xi, xi)                      # [y][x]
+    kmax = int(np.ceil(cfg.force_k + cfg.shell_width))
+    fx = np.zeros((n, n))
+    fy = np.zeros((n, n))
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(-kmax, kmax + 1):
+            km = math.hypot(kx, ky)
+            if km == 0 or abs(km - cfg.force_k) > cfg.shell_width:
+                continue
+            r1 = rng.standard_normal(2)
+            r2 = rng.standard_normal(2)
+            a = r1[0] * kx + r1[1] * ky
+            b = r2[0] * kx + r2[1] * ky
+            ph = kx * X + ky * Y
+            # d/dxi of a cos(ph) + b sin(ph) = (-a sin(ph) + b cos(ph)) * k
+            dphase = -a * np.sin(ph) + b * np.cos(ph)
+            fx += ky * dphase          # dF_e/dy
+            fy -= kx * dphase          # -dF_e/dx
+    rms = math.sqrt(float(np.mean(fx * fx + fy * fy)))
+    scale = (cfg.amplitude / math.sqrt(2.0)) / rms
+    return np.stack([fx, fy]) * scale
 
 
 def observation_points(cfg: CycleConfig) -> np.ndarray:

@@ -320,3 +320,32 @@ def test_observation_layout_and_noise_are_reproducible():
     np.testing.assert_array_equal(a, b)
     assert a.shape == (3, 128)
     assert not np.allclose(a[0], a[1])
+
+
+def test_shell_forcing_is_divergence_free_and_in_its_shell():
+    """Sec. 4.1: F = dx grad(F_e) x i_z is solenoidal and has Fourier support
+    only on ||k| - k_f| <= dk."""
+    cfg = inputs.CONFIGS["paper_physics"].replace(n=64)
+    F = inputs.body_force(cfg)
+    n = cfg.n
+    k1 = np.fft.fftfreq(n, d=1.0 / n)
+    Fx, Fy = np.fft.fft2(F[0]), np.fft.fft2(F[1])
+    div = k1[None, :] * Fx + k1[:, None] * Fy
+    assert np.max(np.abs(div)) < 1e-12 * np.max(np.abs(Fx))
+    kmag = np.hypot(k1[None, :], k1[:, None])
+    outside = np.abs(kmag - cfg.force_k) > cfg.shell_width
+    power = np.abs(Fx) ** 2 + np.abs(Fy) ** 2
+    assert power[outside].sum() < 1e-24 * power.sum()
+    assert math.sqrt(np.mean(F[0] ** 2 + F[1] ** 2)) == pytest.approx(cfg.amplitude / math.sqrt(2),
+                                                                      rel=1e-12)
+    # deterministic from the seed
+    np.testing.assert_array_equal(F, inputs.body_force(cfg))
+
+
+def test_paper_physics_relaxation_time_from_table_1():
+    """tau0 = 1/2 + 3 nu dt / dx^2 with nu = 1e-4, dt = 0.001232, dx = 2 pi / 256."""
+    cfg = inputs.CONFIGS["paper_physics"]
+    nu_lat = (cfg.tau0 - 0.5) / 3
+    assert nu_lat == pytest.approx(1e-4 * 0.001232 / (2 * math.pi / 256) ** 2, rel=1e-12)
+    assert cfg.d_cut == pytest.approx(256 / 8, rel=1e-12)
+    assert cfg.nvar == 3 and cfg.cs == 0.2
