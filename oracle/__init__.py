@@ -28,6 +28,9 @@ Contents and the passage each follows:
 * ``energy_spectrum`` -- shell-summed energy spectrum (Sec. 4.1).
 * ``run_cycles`` -- the workflow of Sec. 3: forecast s steps, observe the
   truth, analyse, repeat.
+* ``oracle.adjoint`` (submodule) -- the gradient of the observation misfit
+  of a forecast with respect to the initial populations and C_s, by a
+  reverse sweep over complex-step partial derivatives of the Sec. 2 step.
 
 Readings of points the paper leaves open (the same readings the GPU path
 documents): the analysis sign is +K (the printed generic update has a sign
