@@ -191,12 +191,61 @@ lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig
  * their localization support, for k < len (larger counts are not reported). */
 lbmletkf_status lbmletkf_local_histogram(void* ctx, int32_t* hist, int32_t len);
 
+/* ---- differentiation form: reverse mode of the Sec. 2 forecast -----------
+ *
+ * Observation misfit of a forecast started from d_f0 (storage layout) with
+ * n_times observation times, steps_per_obs steps apart:
+ *   J(f0, C_s) = sum_{c=1..n_times} sum_m sum_q (H_q(f_m(c steps_per_obs)) - y^o_{c,q})^2,
+ * unweighted, H the observation operator of `observe` (the context's points
+ * and nvar), f(t) the pre-collision state after t steps of the Sec. 2 LBE with
+ * the context's tau0, mu and force.  `cs` is the Smagorinsky constant of the
+ * call -- the parameter J is differentiated with respect to -- and replaces
+ * the context's value for these two calls only.  d_yo: device
+ * [n_times][nvar * n_points] (index q as for letkf_analyze).
+ *
+ * The adjoint workspace (device, caller-owned, 256-byte aligned, at least
+ * lbmletkf_adjoint_workspace_bytes; separate from the context's workspace)
+ * holds the state at every observation time (the checkpoints; a checkpoint
+ * every steps_per_obs steps), the steps_per_obs - 1 states between two
+ * checkpoints that the reverse sweep recomputes, two FP64 adjoint states and
+ * the partial sums.  lbmletkf_misfit_forward writes the checkpoints;
+ * lbmletkf_misfit_backward reads them, so call it after a forward call with
+ * the same d_f0, cs, steps_per_obs, n_times and workspace (checked; the
+ * contents of d_f0, d_yo and the workspace must not change in between, which
+ * is not checked).  A backward call leaves the checkpoints intact and may be
+ * repeated. */
+lbmletkf_status lbmletkf_adjoint_workspace_bytes(const lbmletkf_lbm_params* lbm,
+                                                 int32_t n_points, int32_t steps_per_obs,
+                                                 int32_t n_times, size_t* bytes);
+
+/* Forward sweep: J into d_J[0] (device) and the checkpoints into d_work.
+ * d_f0 is not modified.  steps_per_obs >= 1, n_times >= 1, cs >= 0. */
+lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
+                                        int32_t steps_per_obs, int32_t n_times,
+                                        const double* d_yo, double* d_J, void* d_work,
+                                        size_t work_bytes, void* stream);
+
+/* Reverse sweep (the adjoint of every step, taken at the recomputed forward
+ * states; at |Pi^neq| = 0 the subgradient 0 of the Smagorinsky term is
+ * used): d_grad_f0 (device, canonical FP64 [M][9][ny][nx], overwritten) =
+ * dJ/df0 with respect to the canonical populations of d_f0, and, if
+ * d_grad_cs is not NULL, d_grad_cs[0] = dJ/dC_s.  For F32_DEV storage the
+ * derivative is that of the FP64 step evaluated at the stored states (the
+ * rounding of the stored deviations counts as the identity).  d_grad_f0 must
+ * not overlap d_f0, d_yo or the workspace.  The observation points must be
+ * distinct (LBMLETKF_EUNSUPPORTED otherwise). */
+lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
+                                         int32_t steps_per_obs, int32_t n_times,
+                                         const double* d_yo, void* d_work, size_t work_bytes,
+                                         double* d_grad_f0, double* d_grad_cs, void* stream);
+
 /* Per-stage GPU timing with HIP events on the launch stream.  When enabled,
  * every launch is bracketed by an event pair; lbmletkf_profile_collect waits
  * for them and returns, per stage, the summed milliseconds and launch counts,
- * then clears the record.  Stages: 0 stream-collide, 1 observe, 2 obs
- * statistics, 3 analysis, 4 diagnostics. */
-#define LBMLETKF_NSTAGES 5
+ * then clears the record.  Stages: 0 stream-collide (also the steps of the
+ * misfit sweeps), 1 observe, 2 obs statistics, 3 analysis, 4 diagnostics,
+ * 5 adjoint step, 6 misfit terms. */
+#define LBMLETKF_NSTAGES 7
 lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable);
 lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts);
 

@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(_HERE, "liblbmletkf.so")
 
 LBMLETKF_OK = 0
 DIAG_LEN = 8
-NSTAGES = 5
-STAGES = ("stream_collide", "observe", "obs_stats", "analysis", "diagnostics")
+NSTAGES = 7
+STAGES = ("stream_collide", "observe", "obs_stats", "analysis", "diagnostics", "adjoint",
+          "misfit")
 ROUTE_AUTO, ROUTE_ENSEMBLE, ROUTE_OBSERVATION = 0, 1, 2
 STORAGE_F64, STORAGE_F32_DEV = 0, 1
 
@@ -71,6 +72,13 @@ SIGNATURES = {
     "lbmletkf_info": (_c_int32, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32),
                                  ctypes.POINTER(_c_int32)]),
     "lbmletkf_local_histogram": (_c_int32, [_vp, ctypes.POINTER(_c_int32), _c_int32]),
+    "lbmletkf_adjoint_workspace_bytes": (_c_int32, [ctypes.POINTER(LbmParams), _c_int32,
+                                                    _c_int32, _c_int32,
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmletkf_misfit_forward": (_c_int32, [_vp, _vp, _c_double, _c_int32, _c_int32, _vp, _vp,
+                                           _vp, ctypes.c_size_t, _vp]),
+    "lbmletkf_misfit_backward": (_c_int32, [_vp, _vp, _c_double, _c_int32, _c_int32, _vp, _vp,
+                                            ctypes.c_size_t, _vp, _vp, _vp]),
     "lbmletkf_set_profiling": (_c_int32, [_vp, _c_int32]),
     "lbmletkf_profile_collect": (_c_int32, [_vp, ctypes.POINTER(_c_double),
                                             ctypes.POINTER(ctypes.c_int64)]),
@@ -148,6 +156,88 @@ def run_cycle(ctx: "Context", f: torch.Tensor, nsteps: int, yo: torch.Tensor,
                             _dev(diag, 2 * DIAG_LEN, "diag"), _stream(stream)))
 
 
+def lbmletkf_misfit_forward(ctx: "Context", f0: torch.Tensor, cs: float, steps_per_obs: int,
+                            yo: torch.Tensor, J: torch.Tensor, work: "AdjointWorkspace",
+                            stream=None) -> None:
+    n_times = work.n_times
+    _check(load().lbmletkf_misfit_forward(
+        ctx.handle, ctx._state(f0), float(cs), int(steps_per_obs), int(n_times),
+        _dev(yo, n_times * ctx.n_obs, "yo"), _dev(J, 1, "J"), work.ptr, work.nbytes,
+        _stream(stream)))
+
+
+def lbmletkf_misfit_backward(ctx: "Context", f0: torch.Tensor, cs: float, steps_per_obs: int,
+                             yo: torch.Tensor, work: "AdjointWorkspace", grad_f0: torch.Tensor,
+                             grad_cs: Optional[torch.Tensor] = None, stream=None) -> None:
+    n_times = work.n_times
+    _check(load().lbmletkf_misfit_backward(
+        ctx.handle, ctx._state(f0), float(cs), int(steps_per_obs), int(n_times),
+        _dev(yo, n_times * ctx.n_obs, "yo"), work.ptr, work.nbytes,
+        _dev(grad_f0, ctx.state_numel, "grad_f0"), _dev(grad_cs, 1, "grad_cs"), _stream(stream)))
+
+
+class AdjointWorkspace:
+    """Device workspace of the misfit sweeps (checkpoints, recomputed states,
+    adjoint states) for one (steps_per_obs, n_times)."""
+
+    def __init__(self, ctx: "Context", steps_per_obs: int, n_times: int):
+        n = ctypes.c_size_t(0)
+        _check(load().lbmletkf_adjoint_workspace_bytes(ctypes.byref(ctx._lbm),
+                                                       int(ctx.n_points), int(steps_per_obs),
+                                                       int(n_times), ctypes.byref(n)))
+        self.steps_per_obs, self.n_times = int(steps_per_obs), int(n_times)
+        self.nbytes = int(n.value)
+        self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=ctx.device)
+        self.ptr = (self.buffer.data_ptr() + 255) // 256 * 256
+
+
+class ForecastMisfit(torch.autograd.Function):
+    """J(f0, C_s) of lbmletkf_misfit_forward as an autograd node; its backward
+    is the library's reverse sweep (lbmletkf_misfit_backward)."""
+
+    @staticmethod
+    def forward(actx, f0, cs, ctx, steps_per_obs, yo):
+        cs_val = float(cs)
+        f = ctx.import_canonical(f0.detach().contiguous())
+        yo = yo.detach().contiguous()
+        work = AdjointWorkspace(ctx, steps_per_obs, yo.shape[0])
+        J = torch.empty(1, dtype=torch.float64, device=ctx.device)
+        lbmletkf_misfit_forward(ctx, f, cs_val, steps_per_obs, yo, J, work)
+        ctx._last_forward = (f.data_ptr(), cs_val, int(steps_per_obs), work.ptr)
+        actx.saved = (ctx, f, cs_val, int(steps_per_obs), yo, work)
+        actx.cs_like = cs if torch.is_tensor(cs) else None
+        return J[0]
+
+    @staticmethod
+    def backward(actx, gJ):
+        ctx, f, cs_val, steps, yo, work = actx.saved
+        if ctx._last_forward != (f.data_ptr(), cs_val, steps, work.ptr):
+            # another forward sweep ran on this context since: rebuild the checkpoints
+            J = torch.empty(1, dtype=torch.float64, device=ctx.device)
+            lbmletkf_misfit_forward(ctx, f, cs_val, steps, yo, J, work)
+            ctx._last_forward = (f.data_ptr(), cs_val, steps, work.ptr)
+        g = ctx.new_canonical()
+        gcs = torch.empty(1, dtype=torch.float64, device=ctx.device)
+        lbmletkf_misfit_backward(ctx, f, cs_val, steps, yo, work, g, gcs)
+        gf = g * gJ
+        gc = None
+        if actx.cs_like is not None:
+            gc = (gcs[0] * gJ).to(actx.cs_like.device, actx.cs_like.dtype).reshape(
+                actx.cs_like.shape)
+        return gf, gc, None, None, None
+
+
+def forecast_misfit(ctx: "Context", f0: torch.Tensor, cs, steps_per_obs: int,
+                    yo: torch.Tensor) -> torch.Tensor:
+    """Differentiable J = sum_c sum_m sum_q (H_q(f_m(c s)) - y^o_{c,q})^2.
+
+    f0: canonical FP64 [M][9][ny][nx] CUDA tensor; cs: float or 0-dim tensor
+    (the Smagorinsky constant, differentiable when a tensor); yo:
+    [n_times][n_obs]; s = steps_per_obs.  Gradients flow to f0 and cs.
+    """
+    return ForecastMisfit.apply(f0, cs, ctx, int(steps_per_obs), yo)
+
+
 def plan(nx: int, ny: int, members: int, points, nvar: int, sigma: Sequence[float],
          d_cut: float, beta: float, tau0: float = 0.6, cs: float = 0.1, mu: float = 0.0,
          route: int = ROUTE_AUTO, storage: int = STORAGE_F64) -> Tuple[int, int, int]:
@@ -205,6 +295,8 @@ class Context:
         self.storage = int(storage)
         self.state_dtype = torch.float32 if self.storage == STORAGE_F32_DEV else torch.float64
         self.nx, self.ny, self.members, self.nvar = int(nx), int(ny), int(members), int(nvar)
+        self.tau0, self.cs, self.mu = float(tau0), float(cs), float(mu)
+        self._last_forward = None
         self.plane = self.nx * self.ny
         self.state_numel = self.members * 9 * self.plane
         self.points = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 2))
@@ -325,6 +417,27 @@ class Context:
         buf = (_c_int32 * n)()
         _check(load().lbmletkf_local_histogram(self.handle, buf, n))
         return np.array(buf[:], dtype=np.int64)
+
+    # -- differentiation form ------------------------------------------------------
+    def adjoint_workspace(self, steps_per_obs: int, n_times: int) -> AdjointWorkspace:
+        return AdjointWorkspace(self, steps_per_obs, n_times)
+
+    def misfit_forward(self, f0: torch.Tensor, cs: float, steps_per_obs: int, yo: torch.Tensor,
+                       work: AdjointWorkspace, stream=None) -> torch.Tensor:
+        """J (a 1-element device tensor) and the checkpoints in ``work``."""
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        lbmletkf_misfit_forward(self, f0, cs, steps_per_obs, yo, J, work, stream)
+        self._last_forward = (f0.data_ptr(), float(cs), int(steps_per_obs), work.ptr)
+        return J
+
+    def misfit_backward(self, f0: torch.Tensor, cs: float, steps_per_obs: int,
+                        yo: torch.Tensor, work: AdjointWorkspace,
+                        stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        """(dJ/df0 canonical [M][9][ny][nx], dJ/dC_s 1-element) on the device."""
+        g = self.new_canonical()
+        gcs = torch.empty(1, dtype=torch.float64, device=self.device)
+        lbmletkf_misfit_backward(self, f0, cs, steps_per_obs, yo, work, g, gcs, stream)
+        return g, gcs
 
     def set_profiling(self, enable: bool) -> None:
         _check(load().lbmletkf_set_profiling(self.handle, 1 if enable else 0))

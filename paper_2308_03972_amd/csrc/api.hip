@@ -59,8 +59,18 @@ struct Ctx {
     hipEvent_t join[kSide] = {nullptr, nullptr, nullptr};
     std::vector<int> hist;  // nodes per local-point count
     bool has_force;
+    bool distinct_points = true;  // no two observation points on one node
     char* ws;
     Layout L;
+    // arguments of the last misfit forward sweep (its checkpoints feed the
+    // reverse sweep)
+    struct Fwd {
+        bool valid = false;
+        const void* f0 = nullptr;
+        double cs = 0.0;
+        int steps = 0, times = 0;
+        const void* work = nullptr;
+    } fwd;
     // per-stage timing
     bool profiling = false;
     struct Rec {
@@ -231,6 +241,32 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
     return L;
 }
 
+// Adjoint workspace of the misfit sweeps.
+struct AdjLayout {
+    size_t ckpt, seg, lam0, lam1, jbuf, kpart, total;
+};
+
+AdjLayout make_adj_layout(const lbmletkf_lbm_params* p, int n_points, int steps, int times) {
+    AdjLayout L{};
+    const size_t plane = (size_t)p->nx * p->ny;
+    const size_t sb = plane * 9 * p->members * state_elem_bytes(p->storage);
+    const size_t lb = plane * 9 * p->members * sizeof(double);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.ckpt = take(align_up(sb) * times);
+    L.seg = take(align_up(sb) * (steps - 1));
+    L.lam0 = take(lb);
+    L.lam1 = take(lb);
+    L.jbuf = take((size_t)p->members * n_points * sizeof(double));
+    L.kpart = take((size_t)adjoint_partials({p->nx, p->ny, p->members}) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
 Ctx* as_ctx(void* c) { return reinterpret_cast<Ctx*>(c); }
 
 void release_streams(Ctx* c) {
@@ -320,6 +356,14 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
     c->route = route;
     c->n_eig = n;
     c->has_force = d_force != nullptr;
+    {
+        std::vector<char> seen((size_t)lbm->nx * lbm->ny, 0);
+        for (int k = 0; k < obs->n_points; ++k) {
+            char& v = seen[(size_t)obs->points[2 * k + 1] * lbm->nx + obs->points[2 * k]];
+            if (v) c->distinct_points = false;
+            v = 1;
+        }
+    }
     c->ws = reinterpret_cast<char*>(d_workspace);
     c->L = L;
     c->hist.assign(lmax + 1, 0);
@@ -529,6 +573,159 @@ lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_
     if (d_diag &&
         (st = lbmletkf_diagnostics(ctx, d_f, d_truth_uv, d_diag + LBMLETKF_DIAG_LEN, stream)))
         return st;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_adjoint_workspace_bytes(const lbmletkf_lbm_params* lbm,
+                                                 int32_t n_points, int32_t steps_per_obs,
+                                                 int32_t n_times, size_t* bytes) {
+    lbmletkf_status st = check_lbm(lbm);
+    if (st) return st;
+    if (n_points < 1) return fail(LBMLETKF_EINVAL, "n_points must be >= 1");
+    if (steps_per_obs < 1 || n_times < 1)
+        return fail(LBMLETKF_EINVAL, "steps_per_obs and n_times must be >= 1");
+    if (!bytes) return fail(LBMLETKF_EINVAL, "bytes is NULL");
+    *bytes = make_adj_layout(lbm, n_points, steps_per_obs, n_times).total;
+    return LBMLETKF_OK;
+}
+
+namespace {
+
+lbmletkf_status check_misfit_call(Ctx* c, const void* d_f0, double cs, int steps, int times,
+                                  const double* d_yo, void* d_work, size_t bytes,
+                                  AdjLayout* L) {
+    if (!c || !d_f0 || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (steps < 1 || times < 1)
+        return fail(LBMLETKF_EINVAL, "steps_per_obs and n_times must be >= 1");
+    if (!(cs >= 0.0) || !std::isfinite(cs)) return fail(LBMLETKF_EINVAL, "cs must be >= 0");
+    if (!d_work || (reinterpret_cast<uintptr_t>(d_work) % kAlign))
+        return fail(LBMLETKF_EWORKSPACE, "adjoint workspace must be non-NULL and 256-byte aligned");
+    *L = make_adj_layout(&c->lbm, c->obs.n_points, steps, times);
+    if (bytes < L->total) return fail(LBMLETKF_EWORKSPACE, "adjoint workspace too small");
+    return LBMLETKF_OK;
+}
+
+// State buffers of the misfit sweeps: checkpoint t (t = 0 is f0 itself) and
+// intermediate state j (1 <= j < steps) of the segment being (re)computed.
+struct Sweep {
+    const void* f0;
+    char* w;
+    AdjLayout L;
+    size_t sb;
+    const void* ckpt(int t) const { return t == 0 ? f0 : w + L.ckpt + (size_t)(t - 1) * sb; }
+    void* ckpt_mut(int t) const { return w + L.ckpt + (size_t)(t - 1) * sb; }
+    void* seg(int j) const { return w + L.seg + (size_t)(j - 1) * sb; }
+};
+
+// Steps 1 .. last of the segment that starts at checkpoint t - 1; step
+// `steps` (if last == steps) lands in checkpoint t.
+lbmletkf_status segment_steps(Ctx* c, const Sweep& sw, int t, int steps, int last, double cs,
+                              hipStream_t s) {
+    for (int j = 1; j <= last; ++j) {
+        const void* in = j == 1 ? sw.ckpt(t - 1) : sw.seg(j - 1);
+        void* out = j == steps ? sw.ckpt_mut(t) : sw.seg(j);
+        StageTimer tm(c, kStageCollide, s);
+        hipError_t e = launch_stream_collide(in, out, c->force(), c->dims, c->lbm.tau0, cs,
+                                             c->lbm.mu, c->storage(), s);
+        if (e != hipSuccess) return hip_fail(e, "stream_collide");
+    }
+    return LBMLETKF_OK;
+}
+
+}  // namespace
+
+lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
+                                        int32_t steps_per_obs, int32_t n_times,
+                                        const double* d_yo, double* d_J, void* d_work,
+                                        size_t work_bytes, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    AdjLayout L;
+    lbmletkf_status st =
+        check_misfit_call(c, d_f0, cs, steps_per_obs, n_times, d_yo, d_work, work_bytes, &L);
+    if (st) return st;
+    if (!d_J) return fail(LBMLETKF_EINVAL, "NULL argument");
+    c->fwd.valid = false;
+    hipStream_t s = as_stream(stream);
+    Sweep sw{d_f0, reinterpret_cast<char*>(d_work), L, align_up(c->state_bytes())};
+    double* jbuf = reinterpret_cast<double*>(sw.w + L.jbuf);
+    const size_t nj = (size_t)c->dims.members * c->obs.n_points;
+    hipError_t e = launch_fill(jbuf, nj, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+    for (int t = 1; t <= n_times; ++t) {
+        if ((st = segment_steps(c, sw, t, steps_per_obs, steps_per_obs, cs, s))) return st;
+        StageTimer tm(c, kStageMisfit, s);
+        e = launch_misfit(sw.ckpt(t), c->pts(), c->obs.n_points, c->obs.nvar,
+                          d_yo + (size_t)(t - 1) * c->nobs, nullptr, jbuf, c->dims, c->storage(),
+                          s);
+        if (e != hipSuccess) return hip_fail(e, "misfit");
+    }
+    e = launch_sum(jbuf, nj, 1.0, d_J, s);
+    if (e != hipSuccess) return hip_fail(e, "sum");
+    c->fwd = {true, d_f0, cs, steps_per_obs, n_times, d_work};
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
+                                         int32_t steps_per_obs, int32_t n_times,
+                                         const double* d_yo, void* d_work, size_t work_bytes,
+                                         double* d_grad_f0, double* d_grad_cs, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    AdjLayout L;
+    lbmletkf_status st =
+        check_misfit_call(c, d_f0, cs, steps_per_obs, n_times, d_yo, d_work, work_bytes, &L);
+    if (st) return st;
+    if (!d_grad_f0) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (!c->distinct_points)
+        return fail(LBMLETKF_EUNSUPPORTED, "the misfit gradient needs distinct observation points");
+    const Ctx::Fwd& fw = c->fwd;
+    if (!fw.valid || fw.f0 != d_f0 || fw.cs != cs || fw.steps != steps_per_obs ||
+        fw.times != n_times || fw.work != d_work)
+        return fail(LBMLETKF_EINVAL,
+                    "call lbmletkf_misfit_forward with the same arguments before the backward sweep");
+    const size_t nlam = (size_t)c->dims.members * 9 * c->dims.nx * c->dims.ny;
+    {
+        const char* g0 = reinterpret_cast<const char*>(d_grad_f0);
+        const char* g1 = g0 + nlam * sizeof(double);
+        const char* w0 = reinterpret_cast<const char*>(d_work);
+        const char* f0 = reinterpret_cast<const char*>(d_f0);
+        if ((g0 < w0 + work_bytes && w0 < g1) || (g0 < f0 + c->state_bytes() && f0 < g1))
+            return fail(LBMLETKF_EINVAL, "d_grad_f0 overlaps d_f0 or the workspace");
+    }
+    hipStream_t s = as_stream(stream);
+    Sweep sw{d_f0, reinterpret_cast<char*>(d_work), L, align_up(c->state_bytes())};
+    double* cur = reinterpret_cast<double*>(sw.w + L.lam0);
+    double* oth = reinterpret_cast<double*>(sw.w + L.lam1);
+    double* kpart = reinterpret_cast<double*>(sw.w + L.kpart);
+    const int nparts = adjoint_partials(c->dims);
+    hipError_t e = launch_fill(cur, nlam, 0.0, s);
+    if (e == hipSuccess) e = launch_fill(kpart, (size_t)nparts, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+    for (int t = n_times; t >= 1; --t) {
+        {
+            // lam^(t s) += dJ_t/df at the observation nodes
+            StageTimer tm(c, kStageMisfit, s);
+            e = launch_misfit(sw.ckpt(t), c->pts(), c->obs.n_points, c->obs.nvar,
+                              d_yo + (size_t)(t - 1) * c->nobs, cur, nullptr, c->dims,
+                              c->storage(), s);
+            if (e != hipSuccess) return hip_fail(e, "misfit");
+        }
+        // recompute the states between checkpoints t - 1 and t
+        if ((st = segment_steps(c, sw, t, steps_per_obs, steps_per_obs - 1, cs, s))) return st;
+        for (int j = steps_per_obs - 1; j >= 0; --j) {
+            const void* state = j == 0 ? sw.ckpt(t - 1) : sw.seg(j);
+            double* out = (t == 1 && j == 0) ? d_grad_f0 : oth;
+            StageTimer tm(c, kStageAdjoint, s);
+            e = launch_adjoint_step(state, cur, out, c->force(), c->dims, c->lbm.tau0, cs,
+                                    c->lbm.mu, c->storage(), kpart, s);
+            if (e != hipSuccess) return hip_fail(e, "adjoint_step");
+            std::swap(cur, oth);
+        }
+    }
+    if (d_grad_cs) {
+        // dK/dC_s = 36 sqrt(2) C_s
+        e = launch_sum(kpart, (size_t)nparts, 36.0 * std::sqrt(2.0) * cs, d_grad_cs, s);
+        if (e != hipSuccess) return hip_fail(e, "sum");
+    }
     return LBMLETKF_OK;
 }
 

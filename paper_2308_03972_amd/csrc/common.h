@@ -55,7 +55,7 @@ inline size_t state_elem_bytes(int storage) { return storage == kStoreF32Dev ? 4
 
 // Stage identifiers for per-launch timing.
 enum Stage { kStageCollide = 0, kStageObserve = 1, kStageStats = 2, kStageAnalysis = 3,
-             kStageDiag = 4, kNumStages = 5 };
+             kStageDiag = 4, kStageAdjoint = 5, kStageMisfit = 6, kNumStages = 7 };
 
 struct LbmDims {
     int nx, ny, members;
@@ -110,5 +110,21 @@ hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int sto
                        double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_synth_obs(const double* y, const double* eps, const double* sigma, double* yo,
                             int n, hipStream_t s);
+
+// ---- differentiation form (adjoint.hip) -----------------------------------
+// One reverse step: lam_out (canonical FP64) = adjoint of the step taken from
+// fstate (storage layout) applied to lam_in (canonical FP64); each block adds
+// its share of d(lam_in . step)/dK, K = 18 sqrt(2) C_s^2, to k_partial[block].
+int adjoint_partials(LbmDims d);
+hipError_t launch_adjoint_step(const void* fstate, const double* lam_in, double* lam_out,
+                               const double* force, LbmDims d, double tau0, double cs, double mu,
+                               int storage, double* k_partial, hipStream_t s);
+// Misfit terms at one observation time: jbuf[m * npts + k] += sum_var (H - y^o)^2
+// (jbuf may be NULL); if lam is not NULL, lam += dJ/df at the observation
+// nodes (the points must be distinct).
+hipError_t launch_misfit(const void* f, const int* pts, int npts, int nvar, const double* yo,
+                         double* lam, double* jbuf, LbmDims d, int storage, hipStream_t s);
+hipError_t launch_sum(const double* v, size_t n, double scale, double* out, hipStream_t s);
+hipError_t launch_fill(double* v, size_t n, double value, hipStream_t s);
 
 }  // namespace lbmletkf

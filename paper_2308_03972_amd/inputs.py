@@ -141,6 +141,12 @@ CONFIGS: Dict[str, CycleConfig] = {
         tau0=0.5 + 3.0 * 1e-4 * 0.001232 / (2.0 * math.pi / 256) ** 2, cs=0.2,
         obs_side=8, loc_r=32.0 / math.sqrt(3.0), steps_per_cycle=200, cycles=20,
         mu=5e-4 * 0.001232, nvar=3, forcing="shell"),
+    # Differentiation form: 128^2, 16 members, 8x8 observations of (u, v),
+    # FP32 populations; the misfit covers 10 observation times 20 steps apart
+    # (200 steps, a checkpoint at every observation time).
+    "differentiation": CycleConfig(name="differentiation", n=128, members=16, tau0=0.52,
+                                   cs=0.1, obs_side=8, loc_r=16.0, steps_per_cycle=20,
+                                   cycles=10),
 }
 
 

@@ -108,3 +108,43 @@ def test_workspace_accounts_for_state_and_tables(lib):
     table = cfg.n * cfg.n * 12 * (4 + 8)
     assert state + table < nbytes < state + table + 4 * 2**20
     assert nbytes % 256 == 0
+
+
+def _adjoint_bytes(lib, n, members, storage, n_points, steps, times):
+    import ctypes
+    lbm = binding.LbmParams(n, n, members, 0.52, 0.1, 0.0, storage)
+    out = ctypes.c_size_t(0)
+    st = lib.lbmletkf_adjoint_workspace_bytes(ctypes.byref(lbm), n_points, steps, times,
+                                              ctypes.byref(out))
+    return st, int(out.value)
+
+
+def test_adjoint_workspace_holds_checkpoints_segment_and_adjoints(lib):
+    """Differentiation workload (128^2, 16 members, 64 points, 10 times 20 steps
+    apart): 10 checkpoints + 19 recomputed states in the storage type, two FP64
+    adjoint states, per-(member, point) misfit terms and per-block partials."""
+    def align(v):
+        return (v + 255) // 256 * 256
+    for storage, elem in ((binding.STORAGE_F32_DEV, 4), (binding.STORAGE_F64, 8)):
+        st, nbytes = _adjoint_bytes(lib, 128, 16, storage, 64, 20, 10)
+        assert st == 0
+        plane = 128 * 128
+        state = align(plane * 9 * 16 * elem)
+        expect = (state * 10 + state * 19 + 2 * align(plane * 9 * 16 * 8)
+                  + align(16 * 64 * 8) + align(16 * (plane // 256) * 8))
+        assert nbytes == expect
+    st, _ = _adjoint_bytes(lib, 128, 16, 0, 64, 0, 10)
+    assert st == -1
+    st, _ = _adjoint_bytes(lib, 128, 16, 0, 64, 20, 0)
+    assert st == -1
+    st, _ = _adjoint_bytes(lib, 2, 16, 0, 64, 20, 1)
+    assert st == -2
+
+
+def test_misfit_entries_validate_before_any_gpu_call(lib):
+    import ctypes
+    st = lib.lbmletkf_misfit_forward(None, None, 0.1, 20, 10, None, None, None, 0, None)
+    assert st == -1
+    st = lib.lbmletkf_misfit_backward(None, None, 0.1, 20, 10, None, None, 0, None, None, None)
+    assert st == -1
+    assert b"NULL" in lib.lbmletkf_last_error()
