@@ -28,14 +28,16 @@
  * Lattice units: dx = dt = c = 1.  D2Q9 velocity order
  *   0:(0,0) 1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1) 5:(1,1) 6:(-1,-1) 7:(1,-1) 8:(-1,1).
  *
- * State layouts (members x 9 x ny x nx, x fastest; element type per lbmletkf_storage):
- *   canonical  f[m][a][y][x] = f_a(x, y) of member m, the pre-collision
- *              population of the lattice Boltzmann equation -- the state
- *              vector x(xi) = [f_0 .. f_8] the LETKF updates.
- *   storage    the layout the kernels keep between calls: slot [m][a][y][x]
- *              holds the canonical f_a of node (x + c_ax, y + c_ay), i.e. the
- *              post-collision value streamed by a pull step.  Convert with
- *              lbmletkf_import / lbmletkf_export.
+ * State layouts (M x 9 x ny x nx values):
+ *   canonical  FP64 f[m][a][y][x] = f_a(x, y) of member m, x fastest: the
+ *              pre-collision population of the lattice Boltzmann equation --
+ *              the state vector x(xi) = [f_0 .. f_8] the LETKF updates.
+ *   storage    the layout the kernels keep between calls (element type per
+ *              lbmletkf_storage): f[y][x][a][m], members fastest, where slot
+ *              (node (x, y), a, m) holds the canonical f_a of node
+ *              (x + c_ax, y + c_ay) of member m, i.e. the post-collision value
+ *              streamed by a pull step.  Convert with lbmletkf_import /
+ *              lbmletkf_export.
  * Observation vector index q = nvar * k + var, k = observation point,
  * var = (u, v) for nvar = 2 and (rho, u, v) for nvar = 3.
  *

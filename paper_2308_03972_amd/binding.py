@@ -351,7 +351,8 @@ class Context:
 
     # -- buffers ---------------------------------------------------------------
     def new_state(self) -> torch.Tensor:
-        return torch.empty((self.members, 9, self.ny, self.nx), dtype=self.state_dtype,
+        """A state buffer in the storage layout [y][x][a][member]."""
+        return torch.empty((self.ny, self.nx, 9, self.members), dtype=self.state_dtype,
                            device=self.device)
 
     def new_canonical(self) -> torch.Tensor:

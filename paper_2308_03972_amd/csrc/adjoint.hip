@@ -99,65 +99,64 @@ __device__ __forceinline__ double collide_vjp(const double (&f)[9], const double
     return LK;
 }
 
+// One reverse step, one thread per (node, member) as in the forward kernel.
+// fstate: storage layout; lam_in, lam_out: adjoint states in the canonical
+// node-major layout [node][a][member] (lam(y)_a of member m at slot(y, a, m)).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     const T* __restrict__ fstate, const double* __restrict__ lam_in, double* __restrict__ lam_out,
-    const double* __restrict__ force, int nx, int ny, double tau0, double K, double mu,
-    double* __restrict__ k_partial) {
+    const double* __restrict__ force, int nx, int ny, int members, double tau0, double K,
+    double mu, double* __restrict__ k_partial) {
     const int plane = nx * ny;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int m = blockIdx.y;
+    const int m = threadIdx.x;  // blockDim.x == members
+    const int node = blockIdx.x * blockDim.y + threadIdx.y;
     double lk = 0.0;
-    if (i < plane) {
-        const int y = i / nx, x = i - y * nx;
-        const T* __restrict__ b = fstate + (size_t)m * 9 * plane;
-        const double* __restrict__ li = lam_in + (size_t)m * 9 * plane;
+    if (node < plane) {
+        const int y = node / nx, x = node - y * nx;
         double f[9], L[9], Lf[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            // forward state: canonical f_a(y) is at storage slot y - c_a
-            const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            f[a] = PopIO<T>::load(b + (size_t)a * plane + (size_t)ys * nx + xs, a);
-            // adjoint of f^{n+1}_a at the node this population streams to
-            const int xd = wrap(x + cx_of(a), nx), yd = wrap(y + cy_of(a), ny);
-            L[a] = li[(size_t)a * plane + (size_t)yd * nx + xd];
+            // forward state: canonical f_a(y) is held by the slot of node y - c_a
+            f[a] = PopIO<T>::load(fstate + slot(src_node(x, y, a, nx, ny), a, m, members), a);
+            // adjoint of f^{n+1}_a at the node this population streams to, y + c_a
+            const size_t dst = (size_t)wrap(y + cy_of(a), ny) * nx + wrap(x + cx_of(a), nx);
+            L[a] = lam_in[slot(dst, a, m, members)];
         }
-        const double fx = force ? force[i] : 0.0, fy = force ? force[plane + i] : 0.0;
+        const double fx = force ? force[node] : 0.0, fy = force ? force[plane + node] : 0.0;
         lk = collide_vjp(f, L, tau0, K, fx, fy, mu, Lf);
-        double* __restrict__ lo = lam_out + (size_t)m * 9 * plane + i;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) lo[(size_t)a * plane] = Lf[a];
+        for (int a = 0; a < 9; ++a) lam_out[slot(node, a, m, members)] = Lf[a];
     }
     // per-block sum of dJ/dK, accumulated in this block's own slot (launches
     // on one stream are ordered, so the accumulation is deterministic)
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nthreads = blockDim.x * blockDim.y;
     __shared__ double red[kBlock];
-    red[threadIdx.x] = lk;
+    red[tid] = lk;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if (tid < s && tid + s < nthreads) red[tid] += red[tid + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) k_partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] += red[0];
+    if (tid == 0) k_partial[blockIdx.x] += red[0];
 }
 
-// Misfit at one observation time.  One thread per (member, point): adds
-// (H - y^o)^2 to jbuf[m * npts + k] and, if lam is given, dJ/df at the
-// observation node to the canonical adjoint.
+// Misfit at one observation time.  One thread per (point, member), members
+// fastest: adds (H - y^o)^2 to jbuf[m * npts + k] (if jbuf) and, if lam is
+// given, dJ/df at the observation node to the adjoint state.
 template <typename T>
 __global__ void misfit_kernel(const T* __restrict__ f, const int* __restrict__ pts, int npts,
                               int nvar, const double* __restrict__ yo, double* __restrict__ lam,
                               double* __restrict__ jbuf, int nx, int ny, int members) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts * members) return;
-    const int m = t / npts, k = t - m * npts;
+    const int k = t / members, m = t - k * members;
     const int x = pts[2 * k], y = pts[2 * k + 1];
-    const size_t plane = (size_t)nx * ny;
     double fa[9];
     double rho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-        fa[a] = PopIO<T>::load(f + ((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs, a);
+        fa[a] = PopIO<T>::load(f + slot(src_node(x, y, a, nx, ny), a, m, members), a);
         rho += fa[a];
         jx += cx_of(a) * fa[a];
         jy += cy_of(a) * fa[a];
@@ -173,14 +172,28 @@ __global__ void misfit_kernel(const T* __restrict__ f, const int* __restrict__ p
         ru = u - y0[0];
         rv = v - y0[1];
     }
-    if (jbuf) jbuf[t] += rr * rr + ru * ru + rv * rv;
+    if (jbuf) jbuf[(size_t)m * npts + k] += rr * rr + ru * ru + rv * rv;
     if (lam) {
         // dJ/df_a = 2 rr + 2 ru (c_ax - u)/rho + 2 rv (c_ay - v)/rho
+        const size_t node = (size_t)y * nx + x;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const double g = 2.0 * rr + 2.0 * (ru * (cx_of(a) - u) + rv * (cy_of(a) - v)) / rho;
-            lam[((size_t)m * 9 + a) * plane + (size_t)y * nx + x] += g;
+            lam[slot(node, a, m, members)] += g;
         }
+    }
+}
+
+// Adjoint state [node][a][member] -> canonical public layout [member][a][y][x].
+__global__ void lam_to_canonical_kernel(const double* __restrict__ lam, double* __restrict__ out,
+                                        int plane, int members) {
+    const size_t total = (size_t)plane * 9 * members;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = t % plane;
+        const int a = (int)((t / plane) % 9);
+        const int m = (int)(t / ((size_t)plane * 9));
+        out[t] = lam[slot(i, a, m, members)];
     }
 }
 
@@ -207,22 +220,34 @@ __global__ void fill_kernel(double* __restrict__ v, size_t n, double value) {
 
 }  // namespace
 
-int adjoint_partials(LbmDims d) { return ((d.nx * d.ny + kBlock - 1) / kBlock) * d.members; }
+int adjoint_partials(LbmDims d) {
+    const int npb = nodes_per_block(d.members);
+    return (d.nx * d.ny + npb - 1) / npb;
+}
 
 hipError_t launch_adjoint_step(const void* fstate, const double* lam_in, double* lam_out,
                                const double* force, LbmDims d, double tau0, double cs, double mu,
                                int storage, double* k_partial, hipStream_t s) {
-    const int plane = d.nx * d.ny;
-    dim3 grid((plane + kBlock - 1) / kBlock, d.members);
+    const int npb = nodes_per_block(d.members);
+    const dim3 block(d.members, npb);
+    const dim3 grid(adjoint_partials(d));
     const double K = 18.0 * sqrt(2.0) * cs * cs;
     if (storage == kStoreF32Dev)
-        adjoint_step_kernel<float><<<grid, kBlock, 0, s>>>((const float*)fstate, lam_in, lam_out,
-                                                           force, d.nx, d.ny, tau0, K, mu,
-                                                           k_partial);
+        adjoint_step_kernel<float><<<grid, block, 0, s>>>((const float*)fstate, lam_in, lam_out,
+                                                          force, d.nx, d.ny, d.members, tau0, K,
+                                                          mu, k_partial);
     else
-        adjoint_step_kernel<double><<<grid, kBlock, 0, s>>>((const double*)fstate, lam_in, lam_out,
-                                                            force, d.nx, d.ny, tau0, K, mu,
-                                                            k_partial);
+        adjoint_step_kernel<double><<<grid, block, 0, s>>>((const double*)fstate, lam_in,
+                                                           lam_out, force, d.nx, d.ny, d.members,
+                                                           tau0, K, mu, k_partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_lam_to_canonical(const double* lam, double* out, LbmDims d, hipStream_t s) {
+    const size_t total = (size_t)d.nx * d.ny * 9 * d.members;
+    size_t g = (total + 255) / 256;
+    lam_to_canonical_kernel<<<(int)(g > 65536 ? 65536 : g), 256, 0, s>>>(lam, out, d.nx * d.ny,
+                                                                         d.members);
     return hipGetLastError();
 }
 

@@ -713,14 +713,15 @@ lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
         if ((st = segment_steps(c, sw, t, steps_per_obs, steps_per_obs - 1, cs, s))) return st;
         for (int j = steps_per_obs - 1; j >= 0; --j) {
             const void* state = j == 0 ? sw.ckpt(t - 1) : sw.seg(j);
-            double* out = (t == 1 && j == 0) ? d_grad_f0 : oth;
             StageTimer tm(c, kStageAdjoint, s);
-            e = launch_adjoint_step(state, cur, out, c->force(), c->dims, c->lbm.tau0, cs,
+            e = launch_adjoint_step(state, cur, oth, c->force(), c->dims, c->lbm.tau0, cs,
                                     c->lbm.mu, c->storage(), kpart, s);
             if (e != hipSuccess) return hip_fail(e, "adjoint_step");
             std::swap(cur, oth);
         }
     }
+    e = launch_lam_to_canonical(cur, d_grad_f0, c->dims, s);
+    if (e != hipSuccess) return hip_fail(e, "lam_to_canonical");
     if (d_grad_cs) {
         // dK/dC_s = 36 sqrt(2) C_s
         e = launch_sum(kpart, (size_t)nparts, 36.0 * std::sqrt(2.0) * cs, d_grad_cs, s);

@@ -23,6 +23,23 @@ __host__ __device__ constexpr double w_of(int a) {
 
 constexpr int kWave = 64;
 
+// Population storage layout: [node][a][member], node = y * nx + x, members
+// fastest, so the M values of one population of one node are contiguous and a
+// wavefront of 64 members reads or writes 512 contiguous bytes (FP64).
+__host__ __device__ __forceinline__ size_t slot(size_t node, int a, int m, int members) {
+    return (node * 9 + (size_t)a) * (size_t)members + (size_t)m;
+}
+__host__ __device__ __forceinline__ int wrap1(int i, int n) {
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+// Under pull streaming the canonical f_a of node (x, y) is held by the slot
+// of node (x - c_ax, y - c_ay).
+__host__ __device__ __forceinline__ size_t src_node(int x, int y, int a, int nx, int ny) {
+    return (size_t)wrap1(y - cy_of(a), ny) * nx + wrap1(x - cx_of(a), nx);
+}
+// Node-member launches: blocks of (members, nodes_per_block) threads.
+inline int nodes_per_block(int members) { return members >= 256 ? 1 : 256 / members; }
+
 // Population storage: FP64 values f, or FP32 deviations f - w from the lattice
 // weights (the precision form).  Arithmetic is FP64 in both cases; only the
 // bytes kept in HBM differ.
@@ -112,8 +129,9 @@ hipError_t launch_synth_obs(const double* y, const double* eps, const double* si
                             int n, hipStream_t s);
 
 // ---- differentiation form (adjoint.hip) -----------------------------------
-// One reverse step: lam_out (canonical FP64) = adjoint of the step taken from
-// fstate (storage layout) applied to lam_in (canonical FP64); each block adds
+// One reverse step: lam_out = adjoint of the step taken from fstate (storage
+// layout) applied to lam_in; adjoint states are FP64 in the canonical
+// node-major layout [node][a][member] (unshifted); each block adds
 // its share of d(lam_in . step)/dK, K = 18 sqrt(2) C_s^2, to k_partial[block].
 int adjoint_partials(LbmDims d);
 hipError_t launch_adjoint_step(const void* fstate, const double* lam_in, double* lam_out,
@@ -124,6 +142,8 @@ hipError_t launch_adjoint_step(const void* fstate, const double* lam_in, double*
 // nodes (the points must be distinct).
 hipError_t launch_misfit(const void* f, const int* pts, int npts, int nvar, const double* yo,
                          double* lam, double* jbuf, LbmDims d, int storage, hipStream_t s);
+// Adjoint state [node][a][member] -> canonical [member][a][y][x].
+hipError_t launch_lam_to_canonical(const double* lam, double* out, LbmDims d, hipStream_t s);
 hipError_t launch_sum(const double* v, size_t n, double scale, double* out, hipStream_t s);
 hipError_t launch_fill(double* v, size_t n, double value, hipStream_t s);
 

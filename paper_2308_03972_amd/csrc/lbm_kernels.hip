@@ -2,13 +2,15 @@
 // Smagorinsky eddy viscosity and a body force (Sec. 2), advanced for every
 // ensemble member in one launch.
 //
-// Layout: SoA f[member][a][y][x], FP64, x fastest.  The kernels pull: the
-// thread of node (x, y) gathers f_a from (x - c_a, y - c_a), which is the
+// Layout: f[node][a][member], node = y * nx + x, members fastest (FP64, or
+// FP32 deviations).  One thread per (node, member), a block of
+// (members x nodes) threads.  The kernels pull: the thread of node (x, y)
+// gathers f_a from the slot of node (x - c_ax, y - c_ay), which holds the
 // pre-collision population f_a(x, y, t), collides, and writes f*_a to its own
-// slot (a, y, x).  Between steps a buffer therefore holds post-collision
-// values, and the canonical f_a(x, y) lives at slot (a, y - c_ay, x - c_ax);
-// import/export convert.  Every load and store is coalesced along x (the x
-// shift only misaligns rows by one element).
+// slot (node, a).  Between steps a buffer therefore holds post-collision
+// values, and the canonical f_a(x, y) lives at the slot of node
+// (x - c_ax, y - c_ay); import/export convert.  With 64 members every load
+// and store of a wavefront is 512 contiguous, aligned bytes.
 //
 // Relaxation time: the strain rate is taken from the local non-equilibrium
 // momentum flux Pi = sum_a c_a c_a (f_a - f_a^eq) through the Chapman-Enskog
@@ -58,42 +60,34 @@ __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double
 template <typename T>
 __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
     const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
-    int ny, double tau0, double smag, double mu) {
+    int ny, int members, double tau0, double smag, double mu) {
     const int plane = nx * ny;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= plane) return;
-    const int m = blockIdx.y;
-    const int y = i / nx, x = i - y * nx;
+    const int m = threadIdx.x;  // blockDim.x == members
+    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    if (node >= plane) return;
+    const int y = node / nx, x = node - y * nx;
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-    const T* __restrict__ b = fin + (size_t)m * 9 * plane;
-    const int rc = y * nx, rm = ym * nx, rp = yp * nx;
+    const size_t rc = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
+    // node holding the canonical f_a(x, y): (x - c_ax, y - c_ay)
+    const size_t src[9] = {rc + x,  rc + xm, rc + xp, rm + x, rp + x,
+                           rm + xm, rp + xp, rp + xm, rm + xp};
     // every population is read once and written once per step: stream it
     // past the caches (nontemporal loads and stores)
-    const size_t src[9] = {(size_t)rc + x,
-                           (size_t)1 * plane + rc + xm,
-                           (size_t)2 * plane + rc + xp,
-                           (size_t)3 * plane + rm + x,
-                           (size_t)4 * plane + rp + x,
-                           (size_t)5 * plane + rm + xm,
-                           (size_t)6 * plane + rp + xp,
-                           (size_t)7 * plane + rp + xm,
-                           (size_t)8 * plane + rm + xp};
     double f[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(b + src[a], a);
+    for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(fin + slot(src[a], a, m, members), a);
     double fx = 0.0, fy = 0.0;
     if (force) {
-        fx = force[i];
-        fy = force[plane + i];
+        fx = force[node];
+        fy = force[plane + node];
     }
     collide_node(f, tau0, smag, fx, fy, mu);
-    T* __restrict__ o = fout + (size_t)m * 9 * plane + i;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(o + (size_t)a * plane, a, f[a]);
+    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
 }
 
-// storage slot (a, y, x) <- canonical (a, y + c_ay, x + c_ax)
+// storage slot (node (x, y), a, m) <- canonical [m][a][y + c_ay][x + c_ax]
 template <typename T>
 __global__ void import_kernel(const double* __restrict__ canon, T* __restrict__ f, int nx,
                               int ny, int members) {
@@ -101,15 +95,17 @@ __global__ void import_kernel(const double* __restrict__ canon, T* __restrict__ 
     const size_t total = plane * 9 * members;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = t % plane;
-        const int a = (int)((t / plane) % 9);
-        const int y = (int)(i / nx), x = (int)(i % nx);
-        const int xs = (x + cx_of(a) + nx) % nx, ys = (y + cy_of(a) + ny) % ny;
-        PopIO<T>::store(f + t, a, canon[t - i + (size_t)ys * nx + xs]);
+        const int m = (int)(t % members);
+        const size_t r = t / members;
+        const int a = (int)(r % 9);
+        const size_t node = r / 9;
+        const int y = (int)(node / nx), x = (int)(node % nx);
+        const int xs = wrap1(x + cx_of(a), nx), ys = wrap1(y + cy_of(a), ny);
+        PopIO<T>::store(f + t, a, canon[((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs]);
     }
 }
 
-// canonical (a, y, x) <- storage slot (a, y - c_ay, x - c_ax)
+// canonical [m][a][y][x] <- storage slot (node (x - c_ax, y - c_ay), a, m)
 template <typename T>
 __global__ void export_kernel(const T* __restrict__ f, double* __restrict__ canon, int nx,
                               int ny, int members) {
@@ -119,13 +115,13 @@ __global__ void export_kernel(const T* __restrict__ f, double* __restrict__ cano
          t += (size_t)gridDim.x * blockDim.x) {
         const size_t i = t % plane;
         const int a = (int)((t / plane) % 9);
+        const int m = (int)(t / (plane * 9));
         const int y = (int)(i / nx), x = (int)(i % nx);
-        const int xs = (x - cx_of(a) + nx) % nx, ys = (y - cy_of(a) + ny) % ny;
-        canon[t] = PopIO<T>::load(f + (t - i + (size_t)ys * nx + xs), a);
+        canon[t] = PopIO<T>::load(f + slot(src_node(x, y, a, nx, ny), a, m, members), a);
     }
 }
 
-// f^eq(rho, u) written to the storage slots of node (x, y).
+// f^eq(rho, u) of node (x, y), written to the slots that hold its canonical populations.
 template <typename T>
 __global__ void init_equilibrium_kernel(const double* __restrict__ rho_in,
                                         const double* __restrict__ uv, T* __restrict__ f, int nx,
@@ -134,23 +130,22 @@ __global__ void init_equilibrium_kernel(const double* __restrict__ rho_in,
     const size_t total = plane * members;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = t % plane;
-        const size_t m = t / plane;
+        const int m = (int)(t % members);
+        const size_t i = t / members;
         const int y = (int)(i / nx), x = (int)(i % nx);
-        const double rho = rho_in ? rho_in[t] : 1.0;
-        const double u = uv[(m * 2) * plane + i], v = uv[(m * 2 + 1) * plane + i];
+        const double rho = rho_in ? rho_in[(size_t)m * plane + i] : 1.0;
+        const double u = uv[((size_t)m * 2) * plane + i], v = uv[((size_t)m * 2 + 1) * plane + i];
         const double usq = 1.5 * (u * u + v * v);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const double cu = cx_of(a) * u + cy_of(a) * v;
-            const int xs = (x - cx_of(a) + nx) % nx, ys = (y - cy_of(a) + ny) % ny;
-            PopIO<T>::store(f + ((m * 9 + a) * plane + (size_t)ys * nx + xs), a,
+            PopIO<T>::store(f + slot(src_node(x, y, a, nx, ny), a, m, members), a,
                             rho * w_of(a) * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq));
         }
     }
 }
 
-// rho, u, v of every node from the canonical populations.
+// rho, u, v of every node from the canonical populations: out[m][3][y][x].
 template <typename T>
 __global__ void moments_kernel(const T* __restrict__ f, double* __restrict__ out, int nx,
                                int ny, int members) {
@@ -159,20 +154,20 @@ __global__ void moments_kernel(const T* __restrict__ f, double* __restrict__ out
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
         const size_t i = t % plane;
-        const size_t m = t / plane;
+        const int m = (int)(t / plane);
         const int y = (int)(i / nx), x = (int)(i % nx);
         double rho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const int xs = (x - cx_of(a) + nx) % nx, ys = (y - cy_of(a) + ny) % ny;
-            const double fa = PopIO<T>::load(f + ((m * 9 + a) * plane + (size_t)ys * nx + xs), a);
+            const double fa =
+                PopIO<T>::load(f + slot(src_node(x, y, a, nx, ny), a, m, members), a);
             rho += fa;
             jx += cx_of(a) * fa;
             jy += cy_of(a) * fa;
         }
-        out[(m * 3) * plane + i] = rho;
-        out[(m * 3 + 1) * plane + i] = jx / rho;
-        out[(m * 3 + 2) * plane + i] = jy / rho;
+        out[((size_t)m * 3) * plane + i] = rho;
+        out[((size_t)m * 3 + 1) * plane + i] = jx / rho;
+        out[((size_t)m * 3 + 2) * plane + i] = jy / rho;
     }
 }
 
@@ -186,14 +181,16 @@ int grid_for(size_t total, int block) {
 hipError_t launch_stream_collide(const void* fin, void* fout, const double* force, LbmDims d,
                                  double tau0, double cs, double mu, int storage, hipStream_t s) {
     const int plane = d.nx * d.ny;
-    dim3 grid((plane + kBlock - 1) / kBlock, d.members);
+    const int npb = nodes_per_block(d.members);
+    const dim3 block(d.members, npb);
+    const dim3 grid((plane + npb - 1) / npb);
     const double smag = 18.0 * sqrt(2.0) * cs * cs;
     if (storage == kStoreF32Dev)
-        stream_collide_kernel<float><<<grid, kBlock, 0, s>>>(
-            (const float*)fin, (float*)fout, force, d.nx, d.ny, tau0, smag, mu);
+        stream_collide_kernel<float><<<grid, block, 0, s>>>(
+            (const float*)fin, (float*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
     else
-        stream_collide_kernel<double><<<grid, kBlock, 0, s>>>(
-            (const double*)fin, (double*)fout, force, d.nx, d.ny, tau0, smag, mu);
+        stream_collide_kernel<double><<<grid, block, 0, s>>>(
+            (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
     return hipGetLastError();
 }
 

@@ -36,14 +36,12 @@ __global__ void observe_kernel(const T* __restrict__ f, const int* __restrict__ 
                                int nvar, double* __restrict__ yf, int nx, int ny, int members) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts * members) return;
-    const int m = t / npts, k = t - m * npts;
+    const int k = t / members, m = t - k * members;  // members fastest: contiguous loads
     const int x = pts[2 * k], y = pts[2 * k + 1];
-    const size_t plane = (size_t)nx * ny;
     double rho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-        const double fa = PopIO<T>::load(f + (((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs), a);
+        const double fa = PopIO<T>::load(f + slot(src_node(x, y, a, nx, ny), a, m, members), a);
         rho += fa;
         jx += cx_of(a) * fa;
         jy += cy_of(a) * fa;
@@ -167,9 +165,7 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
     double fv[9], xbar[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-        fv[a] = mem ? PopIO<T>::load(fs + (((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs), a)
-                    : 0.0;
+        fv[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -243,8 +239,7 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < N; ++c) acc += se[a * N + c] * U[c];
-            const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            PopIO<T>::store(fs + (((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs), a,
+            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a,
                             xbar[a] + dmean[a] + acc);
         }
     }
@@ -255,7 +250,8 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
 // density range.  Deterministic two-pass reduction.
 // ---------------------------------------------------------------------------
 constexpr int kDiagBlock = 256;
-constexpr int kDiagNodes = 64;  // nodes per block; 4 member groups per node
+constexpr int kDiagWaves = kDiagBlock / kWave;
+constexpr int kDiagNodes = 64;  // nodes per block: 16 per wavefront, lane = member
 constexpr int kDiagFields = 5;  // err2, spread2, nonfinite, rho_min, rho_max
 
 template <typename T>
@@ -263,82 +259,68 @@ __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
     const T* __restrict__ f, const double* __restrict__ truth_uv, int nx, int ny, int members,
     double* __restrict__ partial) {
     const int plane = nx * ny;
-    const int tx = threadIdx.x & (kDiagNodes - 1);
-    const int g = threadIdx.x / kDiagNodes;  // member group 0..3
-    const int i = blockIdx.x * kDiagNodes + tx;
-    double su = 0.0, sv = 0.0, suu = 0.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
-    if (i < plane) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nodes_per_wave = kDiagNodes / kDiagWaves;
+    double err2 = 0.0, spr2 = 0.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
+    for (int k = 0; k < nodes_per_wave; ++k) {
+        const int i = blockIdx.x * kDiagNodes + wave * nodes_per_wave + k;
+        if (i >= plane) break;
         const int y = i / nx, x = i - y * nx;
-        for (int m = g; m < members; m += 4) {
-            double rho = 0.0, jx = 0.0, jy = 0.0;
+        double u = 0.0, v = 0.0, rho = 1.0;
+        if (lane < members) {
+            double jx = 0.0, jy = 0.0;
+            rho = 0.0;
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
                 const double fa =
-                    PopIO<T>::load(f + (((size_t)m * 9 + a) * plane + (size_t)ys * nx + xs), a);
+                    PopIO<T>::load(f + slot(src_node(x, y, a, nx, ny), a, lane, members), a);
                 rho += fa;
                 jx += cx_of(a) * fa;
                 jy += cy_of(a) * fa;
             }
-            const double u = jx / rho, v = jy / rho;
+            u = jx / rho;
+            v = jy / rho;
             if (!isfinite(rho) || !isfinite(u) || !isfinite(v)) bad += 1.0;
             rmin = fmin(rmin, rho);
             rmax = fmax(rmax, rho);
-            su += u;
-            sv += v;
-            suu += u * u + v * v;
+        }
+        const double ub = wave_sum(u) / members, vb = wave_sum(v) / members;
+        if (truth_uv && lane == 0) {
+            const double du = ub - truth_uv[i], dv = vb - truth_uv[plane + i];
+            err2 += du * du + dv * dv;
+        }
+        if (members > 1) {
+            const double du = lane < members ? u - ub : 0.0, dv = lane < members ? v - vb : 0.0;
+            const double s2 = wave_sum(du * du + dv * dv);
+            if (lane == 0) spr2 += s2 / (members - 1);
         }
     }
-    __shared__ double part[6][kDiagBlock];
-    part[0][threadIdx.x] = su;
-    part[1][threadIdx.x] = sv;
-    part[2][threadIdx.x] = suu;
-    part[3][threadIdx.x] = bad;
-    part[4][threadIdx.x] = rmin;
-    part[5][threadIdx.x] = rmax;
-    __syncthreads();
-    // combine the 4 member groups of each node (fixed order), then the nodes
-    __shared__ double red[kDiagFields][kDiagNodes];
-    if (threadIdx.x < kDiagNodes) {
-        double u = 0.0, v = 0.0, uu = 0.0, b = 0.0, lo = INFINITY, hi = -INFINITY;
-        for (int k = 0; k < 4; ++k) {
-            const int t = k * kDiagNodes + tx;
-            u += part[0][t];
-            v += part[1][t];
-            uu += part[2][t];
-            b += part[3][t];
-            lo = fmin(lo, part[4][t]);
-            hi = fmax(hi, part[5][t]);
-        }
-        double err2 = 0.0, spr2 = 0.0;
-        if (i < plane) {
-            const double ub = u / members, vb = v / members;
-            if (truth_uv) {
-                const double du = ub - truth_uv[i], dv = vb - truth_uv[plane + i];
-                err2 = du * du + dv * dv;
-            }
-            if (members > 1) spr2 = (uu - members * (ub * ub + vb * vb)) / (members - 1);
-        }
-        red[0][tx] = err2;
-        red[1][tx] = spr2;
-        red[2][tx] = b;
-        red[3][tx] = lo;
-        red[4][tx] = hi;
+    // combine: lanes of each wave, then the waves in a fixed order
+    bad = wave_sum(bad);
+    for (int off = 32; off > 0; off >>= 1) {
+        rmin = fmin(rmin, __shfl_xor(rmin, off, kWave));
+        rmax = fmax(rmax, __shfl_xor(rmax, off, kWave));
+    }
+    __shared__ double red[kDiagFields][kDiagWaves];
+    if (lane == 0) {
+        red[0][wave] = err2;
+        red[1][wave] = spr2;
+        red[2][wave] = bad;
+        red[3][wave] = rmin;
+        red[4][wave] = rmax;
     }
     __syncthreads();
-    for (int s = kDiagNodes / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + s];
-            red[1][threadIdx.x] += red[1][threadIdx.x + s];
-            red[2][threadIdx.x] += red[2][threadIdx.x + s];
-            red[3][threadIdx.x] = fmin(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + s]);
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        for (int k = 0; k < kDiagFields; ++k)
-            partial[(size_t)blockIdx.x * kDiagFields + k] = red[k][0];
+        double acc[kDiagFields] = {0.0, 0.0, 0.0, INFINITY, -INFINITY};
+        for (int w = 0; w < kDiagWaves; ++w) {
+            acc[0] += red[0][w];
+            acc[1] += red[1][w];
+            acc[2] += red[2][w];
+            acc[3] = fmin(acc[3], red[3][w]);
+            acc[4] = fmax(acc[4], red[4][w]);
+        }
+        for (int k = 0; k < kDiagFields; ++k) partial[(size_t)blockIdx.x * kDiagFields + k] = acc[k];
     }
 }
 

@@ -63,7 +63,6 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
 
     const int lane = threadIdx.x;
     const int nx = p.nx, ny = p.ny, M = p.members;
-    const int plane = nx * ny;
     const int nz = p.nvar * p.lmax;
     const int item0 = xcd_remap(blockIdx.x, gridDim.x) * SEGS;
     const int seg = lane / N;
@@ -82,12 +81,9 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
         const int x = node % nx, y = node / nx;
         double dx[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-            dx[a] = (valid && mem)
-                        ? PopIO<T>::load(fs + (((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs), a)
-                        : 0.0;
-        }
+        for (int a = 0; a < 9; ++a)
+            dx[a] = (valid && mem) ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a)
+                                   : 0.0;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const double xbar = wave_sum(dx[a]) / M;
@@ -272,11 +268,10 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
         if (mem) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                const int xs = wrap(x - cx_of(a), nx), ys = wrap(y - cy_of(a), ny);
-                T* slot = fs + ((size_t)lane * 9 + a) * plane + (size_t)ys * nx + xs;
-                const double fa = PopIO<T>::load(slot, a);
+                T* sp = fs + slot(src_node(x, y, a, nx, ny), a, lane, M);
+                const double fa = PopIO<T>::load(sp, a);
                 const double xbar = xb[sg * 9 + a];
-                PopIO<T>::store(slot, a, xbar + p.sqrt_beta * (fa - xbar) + dmv[sg * 9 + a] + acc[a]);
+                PopIO<T>::store(sp, a, xbar + p.sqrt_beta * (fa - xbar) + dmv[sg * 9 + a] + acc[a]);
             }
         }
     }

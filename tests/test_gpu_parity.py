@@ -43,10 +43,11 @@ def test_import_export_roundtrip_and_layout():
     back = host(ctx.export_canonical(f))
     np.testing.assert_array_equal(back, canon)
     cx, cy, _ = oracle.lattice()
-    st = host(f)
+    st = host(f)                                    # storage [y][x][a][m]
+    assert st.shape == (23, 37, 9, 3)
     for a in range(9):
-        exp = np.roll(canon[:, a], shift=(-cy[a], -cx[a]), axis=(1, 2))
-        np.testing.assert_array_equal(st[:, a], exp)
+        exp = np.roll(canon[:, a], shift=(-cy[a], -cx[a]), axis=(1, 2))   # [m][y][x]
+        np.testing.assert_array_equal(np.moveaxis(st[:, :, a, :], -1, 0), exp)
 
 
 def test_init_equilibrium_and_moments():

@@ -42,12 +42,13 @@ def test_f32_storage_roundtrip_and_layout():
     _, _, w = oracle.lattice()
     dev = canon - w[None, :, None, None]
     assert np.max(np.abs(back - canon)) <= np.max(np.abs(dev)) * 2.0**-24 * 1.01
-    # stored values are the deviations (in the shifted storage slots)
+    # stored values are the deviations (in the shifted storage slots, [y][x][a][m])
     cx, cy, _ = oracle.lattice()
     st = host(f).astype(np.float64)
     for a in range(9):
         exp = np.roll(dev[:, a], shift=(-cy[a], -cx[a]), axis=(1, 2))
-        np.testing.assert_allclose(st[:, a], exp, rtol=2**-23, atol=1e-12)
+        np.testing.assert_allclose(np.moveaxis(st[:, :, a, :], -1, 0), exp, rtol=2**-23,
+                                   atol=1e-12)
 
 
 def test_f32_stream_collide_step_matches_oracle():
