@@ -103,6 +103,79 @@ def cpu_baseline(cfg, force, pts, sample_steps: int, sample_nodes: int):
     }
 
 
+def differentiation_form(reps: int, storage: int):
+    """Misfit gradient of the differentiation workload (128^2, 16 members, 8x8
+    (u, v) observations, 10 observation times 20 steps apart, a checkpoint at
+    each): forward sweep + reverse sweep, inputs resident on the GPU."""
+    import torch
+    from paper_2308_03972_amd import binding, inputs
+    cfg = inputs.CONFIGS["differentiation"]
+    dev = torch.device("cuda:0")
+    cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    s, times = cfg.steps_per_cycle, cfg.cycles
+    truth_uv, mem_uv = inputs.initial_velocities(cfg)
+    force = cuda(inputs.body_force(cfg))
+    tctx = binding.Context.from_config(cfg, members=1, force=force)
+    ctx = binding.Context.from_config(cfg, force=force, storage=storage)
+    # members and truth spun up one observation interval from their fields
+    f0 = ctx.init_equilibrium(cuda(mem_uv))
+    ctx.step(f0, s)
+    ft = tctx.init_equilibrium(cuda(truth_uv[None]))
+    tctx.step(ft, s)
+    noise = cuda(inputs.all_observation_noise(cfg, times))
+    sig = cuda(inputs.sigma_vector(cfg))
+    yo = torch.empty((times, cfg.n_obs), dtype=torch.float64, device=dev)
+    for c in range(times):
+        tctx.step(ft, s)
+        yo[c] = binding.synth_obs(tctx.observe(ft)[0].contiguous(), noise[c].contiguous(), sig)
+    work = ctx.adjoint_workspace(s, times)
+
+    def one():
+        J = ctx.misfit_forward(f0, cfg.cs, s, yo, work)
+        g, gcs = ctx.misfit_backward(f0, cfg.cs, s, yo, work)
+        return J, g, gcs
+
+    for _ in range(3):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        J, g, gcs = one()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # per-kernel durations: HIP events around every launch, a second pass
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        one()
+    ms, n = ctx.profile_collect()
+    ctx.set_profiling(False)
+    plane = cfg.n * cfg.n
+    elem = 4 if storage == binding.STORAGE_F32_DEV else 8
+    # adjoint step: 9 state loads (storage type), 9 FP64 adjoint loads and 9 stores
+    adj_bytes = (9 * elem + 2 * 9 * 8) * plane * cfg.members
+    t_adj = ms[5] / max(n[5], 1) * 1e-3
+    t_col = ms[0] / max(n[0], 1) * 1e-3
+    gbs = adj_bytes / t_adj / 1e9
+    return {
+        "workload": (f"{cfg.n}x{cfg.n}, {cfg.members} members, {cfg.obs_side}x{cfg.obs_side} "
+                     f"(u,v) observations, {times} observation times {s} steps apart "
+                     f"({times * s} steps, a checkpoint every {s})"),
+        "storage": "FP32 f - w" if elem == 4 else "FP64",
+        "gradients_per_s": round(reps / el, 3),
+        "ms_per_gradient": round(1e3 * el / reps, 4),
+        "launches_per_gradient": {"stream_collide": int(n[0] // reps),
+                                  "adjoint": int(n[5] // reps), "misfit": int(n[6] // reps)},
+        "J": float(J.item()), "dJ_dCs": float(gcs.item()),
+        "grad_f0_norm": float(torch.linalg.vector_norm(g).item()),
+        "stream_collide_avg_us": round(t_col * 1e6, 2),
+        "roofline_adjoint": {"kernel": "adjoint_step", "bound": "hbm", "achieved": round(gbs, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes": int(adj_bytes),
+                             "avg_launch_us": round(t_adj * 1e6, 2)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,7 +185,9 @@ def main() -> int:
     ap.add_argument("--route", default="auto", choices=["auto", "ensemble", "observation"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision form (FP32 population storage) comparison")
+                    help="skip the precision and differentiation forms")
+    ap.add_argument("--grad-reps", type=int, default=20,
+                    help="timed misfit gradients of the differentiation form")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--cpu-nodes", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -196,6 +271,10 @@ def main() -> int:
                                              storage=binding.STORAGE_F32_DEV)
         el32, d32, ms32, n32 = run_form(f32ctx)
         log(f"precision form: timed {args.steps} cycles in {el32:.3f} s")
+        for name, st in (("differentiation", binding.STORAGE_F32_DEV),
+                         ("differentiation_f64", binding.STORAGE_F64)):
+            forms[name] = differentiation_form(args.grad_reps, st)
+            log(f"{name}: {forms[name]['ms_per_gradient']} ms per gradient")
         forms["f32_dev"] = {
             "storage": "FP32 f - w, FP64 arithmetic",
             "cycles_per_s": round(args.steps / el32, 3),
