@@ -41,6 +41,7 @@ struct Bucket {
     int n;       // instantiated eigenproblem size
     int offset;  // into the device node list
     int count;
+    int stream;  // 0: the caller's stream, k > 0: side stream k - 1
 };
 
 struct Ctx {
@@ -377,14 +378,26 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         int maxn = 0;
         for (int sz = 0; sz <= 64; ++sz) {
             if (groups[sz].empty()) continue;
-            c->buckets.push_back({sz, (int)order.size(), (int)groups[sz].size()});
+            c->buckets.push_back({sz, (int)order.size(), (int)groups[sz].size(), 0});
             order.insert(order.end(), groups[sz].begin(), groups[sz].end());
             maxn = sz;
         }
         c->n_eig = maxn;
-        // largest group first: it stays on the caller's stream
+        // Spread the groups over the caller's stream and the side streams by
+        // longest-processing-time-first on an estimated cost (the Jacobi sweeps
+        // grow as N^3 per node, plus a per-node share for the state passes), so
+        // no group waits behind another on one stream while the GPU idles.
+        auto cost = [](const Bucket& b) { return (double)b.count * ((double)b.n * b.n * b.n + 3000.0); };
         std::stable_sort(c->buckets.begin(), c->buckets.end(),
-                         [](const Bucket& a, const Bucket& b) { return a.count > b.count; });
+                         [&](const Bucket& a, const Bucket& b) { return cost(a) > cost(b); });
+        double load[1 + Ctx::kSide] = {0.0, 0.0, 0.0, 0.0};
+        for (Bucket& b : c->buckets) {
+            int best = 0;
+            for (int k = 1; k <= Ctx::kSide; ++k)
+                if (load[k] < load[best]) best = k;
+            b.stream = best;
+            load[best] += cost(b);
+        }
     }
     hipStream_t s = as_stream(stream);
     const size_t plane = (size_t)lbm->nx * lbm->ny;
@@ -532,17 +545,21 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
         // the largest group on the caller's stream, the others forked onto the
         // side streams after everything queued so far, then joined back
         const int nb = (int)c->buckets.size();
+        bool used[Ctx::kSide] = {false, false, false};
+        for (const Bucket& b : c->buckets)
+            if (b.stream > 0) used[b.stream - 1] = true;
         if (nb > 1) e = hipEventRecord(c->fork, s);
-        for (int k = 1; k < nb && e == hipSuccess && k <= Ctx::kSide; ++k)
-            e = hipStreamWaitEvent(c->side[k - 1], c->fork, 0);
+        for (int k = 0; k < Ctx::kSide && e == hipSuccess; ++k)
+            if (used[k]) e = hipStreamWaitEvent(c->side[k], c->fork, 0);
         for (int k = 0; k < nb && e == hipSuccess; ++k) {
             const Bucket& b = c->buckets[k];
-            hipStream_t sk = k == 0 ? s : c->side[(k - 1) % Ctx::kSide];
+            hipStream_t sk = b.stream == 0 ? s : c->side[b.stream - 1];
             e = launch_analysis_obs(p, c->nodes() + b.offset, b.count, b.n, sk);
         }
-        for (int k = 1; k < nb && e == hipSuccess && k <= Ctx::kSide; ++k) {
-            e = hipEventRecord(c->join[k - 1], c->side[k - 1]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join[k - 1], 0);
+        for (int k = 0; k < Ctx::kSide && e == hipSuccess; ++k) {
+            if (!used[k]) continue;
+            e = hipEventRecord(c->join[k], c->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join[k], 0);
         }
     } else {
         e = launch_analysis_ens(p, c->n_eig, s);
