@@ -33,7 +33,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t fbuf, force, loc_pt, loc_g, pts, ybar, dY, dvec, K, yf, partial, counters, nodes, total;
+    size_t fbuf, force, loc_pt, loc_g, pts, ybar, dY, dvec, K, yf, partial, counters, nodes, gbuf,
+        total;
 };
 
 // Nodes of the observation route grouped by eigenproblem size.
@@ -41,7 +42,8 @@ struct Bucket {
     int n;       // instantiated eigenproblem size
     int offset;  // into the device node list
     int count;
-    int stream;  // 0: the caller's stream, k > 0: side stream k - 1
+    int stream;   // 0: the caller's stream, k > 0: side stream k - 1
+    size_t goff;  // offset (doubles) of its per-node G and h in the workspace
 };
 
 struct Ctx {
@@ -99,6 +101,7 @@ struct Ctx {
     double* partial() const { return reinterpret_cast<double*>(ws + L.partial); }
     int* counters() const { return reinterpret_cast<int*>(ws + L.counters); }
     int* nodes() const { return reinterpret_cast<int*>(ws + L.nodes); }
+    double* gbuf() const { return reinterpret_cast<double*>(ws + L.gbuf); }
 };
 
 // RAII event pair around one launch when profiling is on.
@@ -214,8 +217,16 @@ lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_pa
     return LBMLETKF_OK;
 }
 
+// Doubles of per-node G and h the observation route passes between its two
+// kernels: (n^2 + n) per node, n the node's eigenproblem size.
+size_t gbuf_doubles(const std::vector<int>& counts, int nvar) {
+    size_t total = 0;
+    for (int c : counts) total += obs_gbuf_doubles(obs_size_for(even_up(nvar * c)), 1);
+    return total;
+}
+
 Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, int lmax,
-                   int route) {
+                   int route, size_t gbuf) {
     Layout L{};
     const size_t plane = (size_t)p->nx * p->ny;
     const size_t nobs = (size_t)o->n_points * o->nvar;
@@ -238,6 +249,7 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
     L.partial = take((size_t)diag_blocks_for((int)plane) * 8 * sizeof(double));
     L.counters = take(16 * sizeof(int));
     L.nodes = take(plane * sizeof(int));
+    L.gbuf = take(route == 2 ? gbuf * sizeof(double) : 0);
     L.total = off;
     return L;
 }
@@ -309,10 +321,11 @@ lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
     if (st) return st;
     if ((st = check_obs(obs, lbm))) return st;
     if (!bytes) return fail(LBMLETKF_EINVAL, "bytes is NULL");
-    const int lmax = local_counts(lbm, obs, nullptr);
+    std::vector<int> counts;
+    const int lmax = local_counts(lbm, obs, &counts);
     int route = 0, n = 0;
     if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
-    *bytes = make_layout(lbm, obs, lmax, route).total;
+    *bytes = make_layout(lbm, obs, lmax, route, gbuf_doubles(counts, obs->nvar)).total;
     return LBMLETKF_OK;
 }
 
@@ -344,7 +357,7 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
     const int lmax = local_counts(lbm, obs, &counts);
     int route = 0, n = 0;
     if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
-    Layout L = make_layout(lbm, obs, lmax, route);
+    Layout L = make_layout(lbm, obs, lmax, route, gbuf_doubles(counts, obs->nvar));
     if (bytes < L.total) return fail(LBMLETKF_EWORKSPACE, "workspace too small");
 
     Ctx* c = new Ctx();
@@ -378,7 +391,7 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         int maxn = 0;
         for (int sz = 0; sz <= 64; ++sz) {
             if (groups[sz].empty()) continue;
-            c->buckets.push_back({sz, (int)order.size(), (int)groups[sz].size(), 0});
+            c->buckets.push_back({sz, (int)order.size(), (int)groups[sz].size(), 0, 0});
             order.insert(order.end(), groups[sz].begin(), groups[sz].end());
             maxn = sz;
         }
@@ -391,12 +404,15 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         std::stable_sort(c->buckets.begin(), c->buckets.end(),
                          [&](const Bucket& a, const Bucket& b) { return cost(a) > cost(b); });
         double load[1 + Ctx::kSide] = {0.0, 0.0, 0.0, 0.0};
+        size_t goff = 0;
         for (Bucket& b : c->buckets) {
             int best = 0;
             for (int k = 1; k <= Ctx::kSide; ++k)
                 if (load[k] < load[best]) best = k;
             b.stream = best;
             load[best] += cost(b);
+            b.goff = goff;
+            goff += obs_gbuf_doubles(b.n, b.count);
         }
     }
     hipStream_t s = as_stream(stream);
@@ -554,7 +570,8 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
         for (int k = 0; k < nb && e == hipSuccess; ++k) {
             const Bucket& b = c->buckets[k];
             hipStream_t sk = b.stream == 0 ? s : c->side[b.stream - 1];
-            e = launch_analysis_obs(p, c->nodes() + b.offset, b.count, b.n, sk);
+            e = launch_analysis_obs(p, c->nodes() + b.offset, b.count, b.n, c->gbuf() + b.goff,
+                                    sk);
         }
         for (int k = 0; k < Ctx::kSide && e == hipSuccess; ++k) {
             if (!used[k]) continue;

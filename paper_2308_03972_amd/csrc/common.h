@@ -116,11 +116,14 @@ struct AnalysisParams {
 hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s);
 int ens_size_for(int n);              // instantiated size >= n, or 0
 int ens_lds_bytes(int n, int nz);
-// Observation route (l x l dual, size n >= l) for the `count` nodes listed in `nodes`.
+// Observation route (l x l dual, size n >= l) for the `count` nodes listed in
+// `nodes`; gbuf holds obs_gbuf_doubles(n, count) doubles (per-node G and h
+// passed from the eigen kernel to the apply kernel).
 hipError_t launch_analysis_obs(const AnalysisParams& p, const int* nodes, int count, int n,
-                               hipStream_t s);
+                               double* gbuf, hipStream_t s);
 int obs_size_for(int n);              // instantiated size >= n, or 0
-int obs_lds_bytes(int n);
+int obs_lds_bytes(int n);             // the larger of the two kernels' LDS
+size_t obs_gbuf_doubles(int n, int count);
 int diag_blocks_for(int plane);
 
 hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int storage,

@@ -1,19 +1,25 @@
 // Observation-route LETKF analysis (Sec. 3.2.1, Sec. 3.2.2): for a node with
 // l local observations the M x M ensemble-space matrix
 // (M-1)/beta I + Z^T Z (Z = R_loc^-1/2 dY, l x M) is eigendecomposed through
-// its l x l dual Z Z^T: the dual's eigenpairs (lambda_i, u_i) give the
-// eigenpairs ((M-1)/beta + lambda_i, Z^T u_i / sqrt(lambda_i)) and the
-// eigenvalue (M-1)/beta on the orthogonal complement.  Hence
+// its l x l dual S = Z Z^T = U Lambda U^T: the dual's eigenpairs (lambda_i, u_i)
+// give the eigenpairs ((M-1)/beta + lambda_i, Z^T u_i / sqrt(lambda_i)) and
+// the eigenvalue (M-1)/beta on the orthogonal complement.  Hence
 //   w_bar = Z^T U (a + Lambda)^-1 U^T d~,   a = (M-1)/beta,
-//   dW    = sqrt(beta) I + Z^T U phi(Lambda) U^T Z,
+//   dW    = sqrt(beta) I + Z^T G Z,  G = U phi(Lambda) U^T,
 //   phi(l) = (sqrt((M-1)/(a+l)) - sqrt(beta)) / l = -sqrt(beta) / (a s (1+s)),
 //   s = sqrt(1 + l/a)   (cancellation-free, finite at l = 0),
-// and x_m^a = x_bar + sqrt(beta) dX_m + dX w_bar + (dX Z^T) U phi U^T Z_m.
+// and, with B = dX Z^T (9 x l) and h = U (a + Lambda)^-1 U^T d~,
+//   x_m^a = x_bar + sqrt(beta) dX_m + B h + (B G) Z_m.
 //
-// Nodes are grouped by their number of local observations; each group runs
-// the kernel instance whose eigenproblem size N is the smallest instantiated
-// even size >= its l, with 64/N nodes per wavefront (one segment of N lanes
-// per node).  The node list of a group is passed in `nodes`.
+// Two kernels per group of nodes with the same eigenproblem size N (the
+// smallest instantiated even size >= l):
+//   analysis_eig_kernel<N>  64/N nodes per wavefront (a segment of N lanes per
+//     node): local observations, S, the Jacobi eigensolver, and per node the
+//     l x l matrix G and the vector h, written to a buffer;
+//   analysis_apply_kernel   one node per wavefront, lane = member: x_bar, dX,
+//     B, B G, B h and the update of the nine populations.
+// Splitting keeps the register- and LDS-heavy eigensolver apart from the
+// memory-bound state pass, so each runs at its own occupancy.
 #include "common.h"
 #include "device_util.h"
 
@@ -22,136 +28,76 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------------------
-// observation route: SEGS = 64 / N nodes per wavefront, eigenproblem Z Z^T
+// eigen part: SEGS = 64 / N nodes per wavefront
 // ---------------------------------------------------------------------------
 template <int N>
-struct ObsLayout {
+struct EigLayout {
     static_assert(N >= 8 && N % 2 == 0, "eigenproblem size must be even and >= 8");
     static constexpr int SEGS = 64 / N;
-    static constexpr int cmax(int x, int y) { return x > y ? x : y; }
-    // Jacobi rows; stages one node's dX (9 x 64) before, holds E' after
     static constexpr int RS = RowStride<N>::value;
-    static constexpr int kRows = cmax(cmax(SEGS * N * RS, 9 * 64), SEGS * 9 * N);
-    // per segment 10 N doubles: B = dX Z^T as [9][N], later C as [N][10]
-    static constexpr int kBC = SEGS * 10 * N;
-    static constexpr int kVec = 4 * 64;  // cs|red during Jacobi; psi t, h, mean increment after
+    // Jacobi rows (also the convergence partial sums between sweeps), then U
+    static constexpr int kRows = SEGS * N * RS > 128 ? SEGS * N * RS : 128;
+    static constexpr int kVec = 3 * 64;  // (c, s) during Jacobi; psi t, phi, h after
     static constexpr int kObs = 2 * SEGS * N + (SEGS * N + 1) / 2;  // sw, dt, q
-    static constexpr int kXbar = SEGS * 9 + 1;
-    static constexpr int total = kRows + kBC + kVec + kObs + kXbar;
+    static constexpr int total = kRows + kVec + kObs;
 };
 
-template <int N, typename T>
-__global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, const int* nodes,
-                                                          int count, int max_sweeps) {
-    T* __restrict__ fs = reinterpret_cast<T*>(p.f);
-    using L = ObsLayout<N>;
+// Local observation j of `node`: index q into the observation vector, weight
+// sqrt(g / sigma^2) (R_loc^-1/2) and its innovation scaled by that weight.
+__device__ __forceinline__ void local_obs(const AnalysisParams& p, int node, int j, int* q,
+                                          double* w, double* d) {
+    *q = 0;
+    *w = 0.0;
+    if (d) *d = 0.0;
+    if (j >= p.nvar * p.lmax) return;
+    const int slot = j / p.nvar, var = j - slot * p.nvar;
+    const int k = p.loc_pt[(size_t)node * p.lmax + slot];
+    if (k < 0) return;
+    *q = k * p.nvar + var;
+    *w = sqrt(p.loc_g[(size_t)node * p.lmax + slot] * p.rinv[var]);
+    if (d) *d = *w * p.dvec[*q];
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void analysis_eig_kernel(AnalysisParams p, const int* nodes,
+                                                          int count, double* gout,
+                                                          int max_sweeps) {
+    using L = EigLayout<N>;
     constexpr int SEGS = L::SEGS;
+    constexpr int RS = L::RS;
     extern __shared__ double lds[];
     double* rows = lds;                              // [SEGS][N][RS]
-    constexpr int RS = L::RS;
-    double* BC = rows + L::kRows;                    // [SEGS][10 N]
-    double* vec = BC + L::kBC;                       // [4][64]
+    double* vec = rows + L::kRows;                   // [3][64]
     double* sw = vec + L::kVec;                      // [SEGS][N]
     double* dt = sw + SEGS * N;                      // [SEGS][N]
     int* qx = reinterpret_cast<int*>(dt + SEGS * N); // [SEGS][N]
-    double* xb = rows + L::kRows + L::kBC + L::kVec + L::kObs;  // [SEGS][9]
     double2* cs = reinterpret_cast<double2*>(vec);   // Jacobi only
-    double* red = vec + 128;                         // Jacobi only
     double* pt = vec;                                // psi_c t_c
-    double* hv = vec + 64;                           // h_j
-    double* dmv = vec + 128;                         // [SEGS][9] dX w_bar
+    double* phv = vec + 64;                          // phi_c
 
     const int lane = threadIdx.x;
-    const int nx = p.nx, ny = p.ny, M = p.members;
-    const int nz = p.nvar * p.lmax;
-    const int item0 = xcd_remap(blockIdx.x, gridDim.x) * SEGS;
     const int seg = lane / N;
     const int i = lane - seg * N;
     const bool active = seg < SEGS;
     const int sbase = active ? seg * N : 0;
-    const bool mem = lane < M;
-    const int mchunk = (M + SEGS - 1) / SEGS;  // members per lane group in B
+    const int item = xcd_remap(blockIdx.x, gridDim.x) * SEGS + (active ? seg : 0);
+    const bool valid = active && item < count;
+    const int node = valid ? nodes[item] : 0;
 
-    // ---- phase A (one node at a time, lane = member): x_bar, dX, local
-    //      observations and B = dX Z^T (rows of Z: sqrt(r_j) dY[q_j][:])
-#pragma unroll 1
-    for (int sg = 0; sg < SEGS; ++sg) {
-        const bool valid = item0 + sg < count;
-        const int node = valid ? nodes[item0 + sg] : 0;
-        const int x = node % nx, y = node / nx;
-        double dx[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a)
-            dx[a] = (valid && mem) ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a)
-                                   : 0.0;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const double xbar = wave_sum(dx[a]) / M;
-            dx[a] = mem ? dx[a] - xbar : 0.0;
-            if (lane == 0) xb[sg * 9 + a] = xbar;
-        }
-        wave_lds_sync();
-        if (lane < N) {
-            int q = 0;
-            double w = 0.0, d = 0.0;
-            if (valid && lane < nz) {
-                const int slot = lane / p.nvar, var = lane - slot * p.nvar;
-                const int k = p.loc_pt[(size_t)node * p.lmax + slot];
-                if (k >= 0) {
-                    q = k * p.nvar + var;
-                    w = sqrt(p.loc_g[(size_t)node * p.lmax + slot] * p.rinv[var]);
-                    d = w * p.dvec[q];
-                }
-            }
-            qx[sg * N + lane] = q;
-            sw[sg * N + lane] = w;
-            dt[sg * N + lane] = d;
-        }
-        // stage dX of this node ([a][m]) in the not yet used Jacobi rows area
-#pragma unroll
-        for (int a = 0; a < 9; ++a) rows[a * 64 + lane] = dx[a];
-        wave_lds_sync();
-        // lane (g, j): partial sum of B[a][j] over member group g
-        double b[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) b[a] = 0.0;
-        if (active) {
-            const double wj = sw[sg * N + i];
-            if (wj != 0.0) {
-                const double* yrow = p.dY + (size_t)qx[sg * N + i] * M;
-                const int m0 = seg * mchunk;
-                const int m1 = min(M, m0 + mchunk);
-#pragma unroll 2
-                for (int m = m0; m < m1; ++m) {
-                    const double yv = yrow[m];
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) b[a] += rows[a * 64 + m] * yv;
-                }
-            }
-        }
-        // combine the member groups in a fixed order (group 0 keeps the sum)
-#pragma unroll
-        for (int g = 1; g < SEGS; ++g) {
-            const int src = i + g * N;
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                const double v = __shfl(b[a], active ? src : lane, kWave);
-                b[a] += (seg == 0) ? v : 0.0;
-            }
-        }
-        if (lane < N) {
-            const double wj = sw[sg * N + lane];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) BC[sg * 10 * N + a * N + lane] = b[a] * wj;
-        }
-        wave_lds_sync();
+    if (active) {
+        int q = 0;
+        double w = 0.0, d = 0.0;
+        if (valid) local_obs(p, node, i, &q, &w, &d);
+        qx[lane] = q;
+        sw[lane] = w;
+        dt[lane] = d;
     }
-
-    // ---- phase B: S = Z Z^T = diag(sw) K diag(sw) on the local observations
+    wave_lds_sync();
+    // S = Z Z^T = diag(sw) K diag(sw) on the local observations
     double S[N], U[N];
     {
-        const double wi = active ? sw[sbase + i] : 0.0;
-        const double* Krow = p.K + (size_t)(active ? qx[sbase + i] : 0) * p.nobs;
+        const double wi = active ? sw[lane] : 0.0;
+        const double* Krow = p.K + (size_t)(active ? qx[lane] : 0) * p.nobs;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const double wk = sw[sbase + k];
@@ -159,12 +105,10 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
             U[k] = (k == i && active) ? 1.0 : 0.0;
         }
     }
-
-    // ---- phase C: eigendecomposition
-    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, max_sweeps);
+    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, rows, lane, max_sweeps);
     if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
 
-    // ---- phase D: eigenvalue functions, U to LDS, t = U^T d~, h = U psi t
+    // eigenvalue functions, U to LDS, t = U^T d~, h = U psi t, G = U phi U^T
     const double lam = extract_lane_entry<N>(S, i);
     const double sq = sqrt(1.0 + lam / p.a);
     const double psi = 1.0 / (p.a + lam);
@@ -175,6 +119,7 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
 #pragma unroll
         for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
     }
+    phv[lane] = active ? phi : 0.0;
     wave_lds_sync();
     {
         double t = 0.0;
@@ -183,110 +128,192 @@ __global__ __launch_bounds__(64) void analysis_obs_kernel(AnalysisParams p, cons
         pt[lane] = active ? psi * t : 0.0;
     }
     wave_lds_sync();
-    {
-        double h = 0.0;
+    double h = 0.0;
 #pragma unroll
-        for (int c = 0; c < N; ++c) h += U[c] * pt[sbase + c];
-        hv[lane] = active ? h : 0.0;
-    }
-    // ---- phase E: e = (B U)[:, i]; mean increment dm = B h (lanes a < 9)
-    double e[9];
+    for (int c = 0; c < N; ++c) h += U[c] * pt[sbase + c];
+    // row i of U phi, in place
 #pragma unroll
-    for (int a = 0; a < 9; ++a) e[a] = 0.0;
-    if (active) {
-        const double* Bs = BC + seg * 10 * N;
-        for (int k = 0; k < N; ++k) {
-            const double ukc = rows[(size_t)(sbase + k) * RS + i];
+    for (int c = 0; c < N; ++c) U[c] *= phv[sbase + c];
+    if (valid) {
+        // lane i computes G_ij = sum_c U_ic phi_c U_jc and stores it at (j, i):
+        // consecutive lanes write consecutive addresses
+        double* out = gout + (size_t)item * (N * N + N);
+#pragma unroll 1
+        for (int j = 0; j < N; ++j) {
+            const double2* rj = reinterpret_cast<const double2*>(rows + (size_t)(sbase + j) * RS);
+            double g = 0.0;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) e[a] += Bs[a * N + k] * ukc;
-        }
-    }
-    wave_lds_sync();  // h visible
-    // population a = i, i + N, ... of the mean increment (N may be < 9)
-    double dm[2] = {0.0, 0.0};
-    if (active) {
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int a = i + r * N;
-            if (a < 9) {
-                const double* Bs = BC + seg * 10 * N + a * N;
-                for (int j = 0; j < N; ++j) dm[r] += Bs[j] * hv[sbase + j];
+            for (int c = 0; c < N / 2; ++c) {
+                const double2 r = rj[c];
+                g += U[2 * c] * r.x + U[2 * c + 1] * r.y;
             }
+            out[(size_t)j * N + i] = g;
         }
+        out[(size_t)N * N + i] = h;
     }
-    wave_lds_sync();  // all reads of U (rows) done
-    if (active) {
+}
+
+// ---------------------------------------------------------------------------
+// apply part: one node per wavefront, lane = member
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int apply_lds_doubles(int n) {
+    // G and h, dX [9][64], B [9][n], C [n][10], sw [n], mean increment [9],
+    // x_bar [9], q [n]
+    return n * n + n + 9 * 64 + 9 * n + 10 * n + n + 9 + 9 + (n + 1) / 2;
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(64) void analysis_apply_kernel(AnalysisParams p, const int* nodes,
+                                                            int count,
+                                                            const double* __restrict__ gin) {
+    constexpr int n = N;
+    constexpr int groups = kWave / N;                  // member groups in B
+    constexpr int kChunk = (kWave + groups - 1) / groups;
+    T* __restrict__ fs = reinterpret_cast<T*>(p.f);
+    extern __shared__ double lds[];
+    double* Gs = lds;                                  // [n][n] as stored: (k, j) = G_jk
+    double* hs = Gs + n * n;                           // [n]
+    double* dxs = hs + n;                              // [9][64]
+    double* Bs = dxs + 9 * 64;                         // [9][n]
+    double* Cs = Bs + 9 * n;                           // [n][10]
+    double* sw = Cs + 10 * n;                          // [n]
+    double* dmv = sw + n;                              // [9]
+    double* xbv = dmv + 9;                             // [9]
+    int* qx = reinterpret_cast<int*>(xbv + 9);         // [n]
+
+    const int lane = threadIdx.x;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= count) return;                         // uniform over the wavefront
+    const int node = nodes[item];
+    const int nx = p.nx, ny = p.ny, M = p.members;
+    const bool mem = lane < M;
+    const int x = node % nx, y = node / nx;
+
+    // independent loads first: the nine populations, G and h, the local observations
+    double dx[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) rows[(seg * 9 + a) * N + i] = phi * e[a];  // E'
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-            if (i + r * N < 9) dmv[seg * 9 + i + r * N] = dm[r];
+    for (int a = 0; a < 9; ++a)
+        dx[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
+    const double* g = gin + (size_t)item * (n * n + n);
+    for (int t = lane; t < n * n + n; t += kWave) Gs[t] = g[t];
+    for (int j = lane; j < n; j += kWave) {
+        int q;
+        double w;
+        local_obs(p, node, j, &q, &w, nullptr);
+        qx[j] = q;
+        sw[j] = w;
     }
     wave_lds_sync();
-    // ---- phase F: C = E' U^T (own row of U)
-    double cj[9];
+    // x_bar and dX of the nine populations
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        double acc = 0.0;
-        if (active) {
-#pragma unroll
-            for (int c = 0; c < N; ++c) acc += rows[(seg * 9 + a) * N + c] * U[c];
-        }
-        cj[a] = acc;
-    }
-    wave_lds_sync();  // all reads of B done (phase E) -- overwrite with C
-    if (active) {
-        double* Cj = BC + seg * 10 * N + i * 10;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) Cj[a] = cj[a];
-        Cj[9] = 0.0;
+        const double xbar = wave_sum(dx[a]) / M;
+        dx[a] = mem ? dx[a] - xbar : 0.0;
+        dxs[a * 64 + lane] = dx[a];
+        if (lane == 0) xbv[a] = xbar;
     }
     wave_lds_sync();
-
-    // ---- phase G (one node at a time, lane = member): apply and store
-#pragma unroll 1
-    for (int sg = 0; sg < SEGS; ++sg) {
-        if (item0 + sg >= count) break;
-        const int node = nodes[item0 + sg];
-        const int x = node % nx, y = node / nx;
+    // B[a][j] = w_j sum_m dX_a(m) dY[q_j][m]: lane (group, j) sums a member
+    // range (its dY values loaded together first), the groups are combined in a
+    // fixed order
+    const int gi = lane / n, j = lane - gi * n;
+    const bool gact = gi < groups;
+    double b[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) b[a] = 0.0;
+    if (gact && sw[j] != 0.0) {
+        const int mchunk = (M + groups - 1) / groups;
+        const int m0 = gi * mchunk;
+        const int m1 = min(M, m0 + mchunk);
+        const double* yrow = p.dY + (size_t)qx[j] * M;
+        double yv[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) yv[t] = m0 + t < m1 ? yrow[m0 + t] : 0.0;
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            const int m = m0 + t < m1 ? m0 + t : m0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) b[a] += dxs[a * 64 + m] * yv[t];
+        }
+    }
+    for (int gg = 1; gg < groups; ++gg) {
+        const int src = gact ? j + gg * n : lane;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const double v = __shfl(b[a], src, kWave);
+            b[a] += (gi == 0) ? v : 0.0;
+        }
+    }
+    if (lane < n) {
+        const double wj = sw[lane];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) Bs[a * n + lane] = b[a] * wj;
+    }
+    wave_lds_sync();
+    // C = B G ([j][a]) and the mean increment B h
+    for (int jj = lane; jj < n; jj += kWave) {
+        double c[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) c[a] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double gkj = Gs[k * n + jj];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) c[a] += Bs[a * n + k] * gkj;
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) Cs[jj * 10 + a] = c[a];
+        Cs[jj * 10 + 9] = 0.0;
+    }
+    if (lane < 9) {
+        double d = 0.0;
+        for (int k = 0; k < n; ++k) d += Bs[lane * n + k] * hs[k];
+        dmv[lane] = d;
+    }
+    wave_lds_sync();
+    if (mem) {
+        // this member's l observation perturbations, loaded together
+        double z[N];
+#pragma unroll
+        for (int jj = 0; jj < N; ++jj) {
+            const double wj = sw[jj];
+            z[jj] = wj != 0.0 ? wj * p.dY[(size_t)qx[jj] * M + lane] : 0.0;
+        }
         double acc[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) acc[a] = 0.0;
-        const double* Cs = BC + sg * 10 * N;
-#pragma unroll 2
-        for (int j = 0; j < N; ++j) {
-            const double wj = sw[sg * N + j];
-            const double z = (mem && wj != 0.0) ? wj * p.dY[(size_t)qx[sg * N + j] * M + lane] : 0.0;
-            const double2* c2 = reinterpret_cast<const double2*>(Cs + j * 10);
 #pragma unroll
-            for (int h = 0; h < 5; ++h) {
-                const double2 v = c2[h];
-                acc[2 * h] += v.x * z;
-                if (2 * h + 1 < 9) acc[2 * h + 1] += v.y * z;
-            }
-        }
-        if (mem) {
+        for (int jj = 0; jj < N; ++jj) {
+            const double2* c2 = reinterpret_cast<const double2*>(Cs + jj * 10);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                T* sp = fs + slot(src_node(x, y, a, nx, ny), a, lane, M);
-                const double fa = PopIO<T>::load(sp, a);
-                const double xbar = xb[sg * 9 + a];
-                PopIO<T>::store(sp, a, xbar + p.sqrt_beta * (fa - xbar) + dmv[sg * 9 + a] + acc[a]);
+            for (int hh = 0; hh < 5; ++hh) {
+                const double2 cv = c2[hh];
+                acc[2 * hh] += cv.x * z[jj];
+                if (2 * hh + 1 < 9) acc[2 * hh + 1] += cv.y * z[jj];
             }
+            if (jj % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
+#pragma unroll
+        for (int a = 0; a < 9; ++a)
+            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a,
+                            xbv[a] + p.sqrt_beta * dx[a] + dmv[a] + acc[a]);
     }
 }
 
 template <int N>
-hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, hipStream_t s) {
-    using L = ObsLayout<N>;
-    const size_t bytes = (size_t)L::total * sizeof(double);
-    const int blocks = (count + L::SEGS - 1) / L::SEGS;
-    if (blocks == 0) return hipSuccess;
+hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double* gbuf,
+                    hipStream_t s) {
+    using L = EigLayout<N>;
+    if (count == 0) return hipSuccess;
+    const size_t eig_bytes = (size_t)L::total * sizeof(double);
+    const int eig_blocks = (count + L::SEGS - 1) / L::SEGS;
+    analysis_eig_kernel<N><<<eig_blocks, 64, eig_bytes, s>>>(p, nodes, count, gbuf, 30);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
     if (p.storage == kStoreF32Dev)
-        analysis_obs_kernel<N, float><<<blocks, 64, bytes, s>>>(p, nodes, count, 30);
+        analysis_apply_kernel<N, float><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
     else
-        analysis_obs_kernel<N, double><<<blocks, 64, bytes, s>>>(p, nodes, count, 30);
+        analysis_apply_kernel<N, double><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
     return hipGetLastError();
 }
 
@@ -308,17 +335,21 @@ int obs_size_for(int n) {
 
 int obs_lds_bytes(int n) {
     switch (n) {
-#define X(v) case v: return ObsLayout<v>::total * (int)sizeof(double);
+#define X(v) case v: return (EigLayout<v>::total > apply_lds_doubles(v) ? EigLayout<v>::total \
+                                                                      : apply_lds_doubles(v)) * \
+                            (int)sizeof(double);
         LBMLETKF_OBS_SIZES(X)
 #undef X
         default: return 1 << 30;
     }
 }
 
+size_t obs_gbuf_doubles(int n, int count) { return (size_t)count * ((size_t)n * n + n); }
+
 hipError_t launch_analysis_obs(const AnalysisParams& p, const int* nodes, int count, int n,
-                               hipStream_t s) {
+                               double* gbuf, hipStream_t s) {
     switch (n) {
-#define X(v) case v: return launch_n<v>(p, nodes, count, s);
+#define X(v) case v: return launch_n<v>(p, nodes, count, gbuf, s);
         LBMLETKF_OBS_SIZES(X)
 #undef X
         default: return hipErrorInvalidValue;

@@ -106,7 +106,13 @@ def test_workspace_accounts_for_state_and_tables(lib):
                                      cfg.nvar, cfg.sigmas, cfg.d_cut, cfg.beta)
     state = cfg.n * cfg.n * 9 * cfg.members * 8
     table = cfg.n * cfg.n * 12 * (4 + 8)
-    assert state + table < nbytes < state + table + 4 * 2**20
+    # per-node G (n x n) and h (n) between the two analysis kernels, n the
+    # eigenproblem size of the node's local-observation count
+    lmax, _, _ = binding.plan(cfg.n, cfg.n, cfg.members, inputs.observation_points(cfg),
+                              cfg.nvar, cfg.sigmas, cfg.d_cut, cfg.beta)
+    gmin = cfg.n * cfg.n * (16 * 16 + 16) * 8
+    gmax = cfg.n * cfg.n * (24 * 24 + 24) * 8
+    assert state + table + gmin < nbytes < state + table + gmax + 4 * 2**20
     assert nbytes % 256 == 0
 
 
