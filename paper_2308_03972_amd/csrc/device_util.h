@@ -86,11 +86,19 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
         const double aqq = segrows[(size_t)(p + 1) * RS + p + 1];
         const double apq = segrows[(size_t)p * RS + p + 1];
         if (apq != 0.0) {
-            // smaller root of t^2 + 2 tau t - 1 = 0, tau = (aqq - app) / (2 apq), written
-            // without forming tau: t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app
+            // t = sgn(tau) / (|tau| + sqrt(1 + tau^2)), tau = (aqq - app) / (2 apq),
+            // the smaller root of t^2 + 2 tau t - 1 = 0, evaluated in FP32 on
+            // operands scaled so that |apq| is near [1, 2): any t gives an exactly
+            // orthogonal rotation through c and s below (FP64), and an FP32-accurate
+            // t still removes all but ~1e-7 of a_pq, which the next sweeps finish
             const double d = aqq - app;
-            const double den = fabs(d) + sqrt(d * d + 4.0 * apq * apq);
-            const double t = (d < 0.0 ? -2.0 * apq : 2.0 * apq) / den;
+            const double sc = ldexp(1.0, -max(ilogb(apq), -1000));
+            const float af = (float)(apq * sc);
+            const float at = fabsf((float)(d * sc)) * 0.5f * __builtin_amdgcn_rcpf(fabsf(af));
+            float tf = at > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(at)
+                                  : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(1.0f + at * at));
+            if ((d < 0.0) != (apq < 0.0)) tf = -tf;
+            const double t = (double)tf;
             c = rsqrt(1.0 + t * t);
             s = t * c;
         }
