@@ -241,6 +241,67 @@ lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
                                          const double* d_yo, void* d_work, size_t work_bytes,
                                          double* d_grad_f0, double* d_grad_cs, void* stream);
 
+/* ---- batching form: many independent problems per cycle -----------------
+ *
+ * A batch binds n contexts (problems of any grid, ensemble size and observing
+ * network; members must divide 256 and every context must have the same
+ * storage) to their state buffers d_f[k] and advances all of them one cycle
+ * (Sec. 3 workflow (ii)-(iv), as run_cycle without diagnostics) per call:
+ *   - the forecast of all problems is one persistent launch per step over the
+ *     concatenated (problem, node tile) list;
+ *   - H and the observation statistics run per problem;
+ *   - the analyses are grouped across problems by eigenproblem size (one
+ *     eigen + one apply launch, or one ensemble-route launch, per size),
+ *     spread over the launch stream and three batch-owned side streams;
+ *   - with use_graph, the whole cycle is captured once as a hipGraph and
+ *     replayed by every lbmletkf_batch_run_cycle.
+ * The results are those of run_cycle on each context (same kernels' per-node
+ * arithmetic).  The batch uses each context's workspace (ping-pong partner,
+ * tables, statistics) and its own workspace (caller-owned, 256-byte aligned,
+ * >= lbmletkf_batch_workspace_bytes) for the per-problem parameters, forecast
+ * task lists, observation slots, the analysis node lists, wave lists and G
+ * buffers.  The contexts, state buffers and both workspaces must outlive the
+ * batch; a context must not run other calls concurrently with its batch. */
+typedef struct {
+    int32_t forecast_blocks;    /* persistent blocks of the forecast launch, 1..2^20 */
+    int32_t tile_rows;          /* forecast tile = tile_rows x (256 / M) nodes, 1..64 */
+    int32_t bucket_granularity; /* eigenproblem sizes rounded up to multiples of 2, 4 or 8 */
+    int32_t use_graph;          /* 1: capture the cycle once as a hipGraph and replay it */
+} lbmletkf_batch_config;
+
+lbmletkf_status lbmletkf_batch_workspace_bytes(void* const* ctxs, int32_t n, size_t* bytes);
+
+/* Create a batch of n contexts with states d_f[k] (device, storage layout) and
+ * nsteps forecast steps per cycle.  ctxs and d_f are host arrays of n pointers.
+ * cfg may be NULL: {1024 blocks, 1 tile row, granularity 2, graph}.  Waits for
+ * its setup copies and, with use_graph, captures the cycle. */
+lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32_t n,
+                                      int32_t nsteps, const lbmletkf_batch_config* cfg,
+                                      void* d_workspace, size_t bytes, void* stream,
+                                      void** batch_out);
+
+/* One cycle of every problem.  d_yo: host array of n device pointers, d_yo[k]
+ * = this cycle's observations of problem k ([nvar * n_points], copied in on
+ * `stream` before the cycle). */
+lbmletkf_status lbmletkf_batch_run_cycle(void* batch, const double* const* d_yo, void* stream);
+
+lbmletkf_status lbmletkf_batch_get_config(void* batch, lbmletkf_batch_config* cfg);
+
+/* Re-tile, re-group and (with use_graph) re-capture; waits for its setup. */
+lbmletkf_status lbmletkf_batch_set_config(void* batch, const lbmletkf_batch_config* cfg,
+                                          void* stream);
+
+/* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048}) x
+ * (tile_rows in {1, 2, 4, 8}) forecast step and every bucket granularity
+ * {2, 4, 8} of the analysis (reps timed runs each, HIP events), then applies
+ * the fastest with use_graph = 1.  Runs on the contexts' ping-pong partner
+ * buffers: the bound states are not modified.  Outputs (any may be NULL): the
+ * chosen configuration, its forecast ms per step and analysis ms per cycle. */
+lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_config* best,
+                                    double* forecast_ms, double* analysis_ms, void* stream);
+
+lbmletkf_status lbmletkf_batch_destroy(void* batch);
+
 /* Per-stage GPU timing with HIP events on the launch stream.  When enabled,
  * every launch is bracketed by an event pair; lbmletkf_profile_collect waits
  * for them and returns, per stage, the summed milliseconds and launch counts,

@@ -43,6 +43,14 @@ class ObsParams(ctypes.Structure):
                 ("beta", _c_double), ("route", _c_int32)]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("forecast_blocks", _c_int32), ("tile_rows", _c_int32),
+                ("bucket_granularity", _c_int32), ("use_graph", _c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class LbmLetkfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"lbmletkf status {status}: {msg}")
@@ -79,6 +87,18 @@ SIGNATURES = {
                                            _vp, ctypes.c_size_t, _vp]),
     "lbmletkf_misfit_backward": (_c_int32, [_vp, _vp, _c_double, _c_int32, _c_int32, _vp, _vp,
                                             ctypes.c_size_t, _vp, _vp, _vp]),
+    "lbmletkf_batch_workspace_bytes": (_c_int32, [ctypes.POINTER(_vp), _c_int32,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmletkf_batch_create": (_c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _c_int32,
+                                         _c_int32, ctypes.POINTER(BatchConfig), _vp,
+                                         ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "lbmletkf_batch_run_cycle": (_c_int32, [_vp, ctypes.POINTER(_vp), _vp]),
+    "lbmletkf_batch_get_config": (_c_int32, [_vp, ctypes.POINTER(BatchConfig)]),
+    "lbmletkf_batch_set_config": (_c_int32, [_vp, ctypes.POINTER(BatchConfig), _vp]),
+    "lbmletkf_batch_tune": (_c_int32, [_vp, _c_int32, ctypes.POINTER(BatchConfig),
+                                       ctypes.POINTER(_c_double), ctypes.POINTER(_c_double),
+                                       _vp]),
+    "lbmletkf_batch_destroy": (_c_int32, [_vp]),
     "lbmletkf_set_profiling": (_c_int32, [_vp, _c_int32]),
     "lbmletkf_profile_collect": (_c_int32, [_vp, ctypes.POINTER(_c_double),
                                             ctypes.POINTER(ctypes.c_int64)]),
@@ -448,3 +468,71 @@ class Context:
         cnt = (ctypes.c_int64 * NSTAGES)()
         _check(load().lbmletkf_profile_collect(self.handle, ms, cnt))
         return np.array(ms[:]), np.array(cnt[:])
+
+
+class Batch:
+    """Many contexts advanced together (lbmletkf_batch_*): one persistent
+    forecast launch per step for all problems, analyses grouped by eigenproblem
+    size across problems, the cycle captured as a hipGraph."""
+
+    def __init__(self, contexts: Sequence[Context], states: Sequence[torch.Tensor], nsteps: int,
+                 config: Optional[dict] = None, stream=None):
+        lib = load()
+        if len(contexts) != len(states) or not contexts:
+            raise ValueError("need one state per context")
+        self.contexts = list(contexts)
+        self.states = list(states)
+        self.nsteps = int(nsteps)
+        n = len(contexts)
+        self._ctxs = (_vp * n)(*[c.handle.value for c in contexts])
+        self._fs = (_vp * n)(*[c._state(f) for c, f in zip(contexts, states)])
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.lbmletkf_batch_workspace_bytes(self._ctxs, n, ctypes.byref(nbytes)))
+        dev = contexts[0].device
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        cfg = None
+        if config is not None:
+            cfg = BatchConfig(**{k: int(v) for k, v in config.items()})
+        h = _vp()
+        _check(lib.lbmletkf_batch_create(self._ctxs, self._fs, n, self.nsteps,
+                                         ctypes.byref(cfg) if cfg is not None else None, aligned,
+                                         ctypes.c_size_t(nbytes.value), _stream(stream),
+                                         ctypes.byref(h)))
+        self.handle = h
+
+    def run_cycle(self, yo: Sequence[torch.Tensor], stream=None) -> None:
+        n = len(self.contexts)
+        if len(yo) != n:
+            raise ValueError("need one observation vector per problem")
+        ptrs = (_vp * n)(*[_dev(y, c.n_obs, "yo") for c, y in zip(self.contexts, yo)])
+        self._yo_keep = list(yo)
+        _check(load().lbmletkf_batch_run_cycle(self.handle, ptrs, _stream(stream)))
+
+    @property
+    def config(self) -> dict:
+        cfg = BatchConfig()
+        _check(load().lbmletkf_batch_get_config(self.handle, ctypes.byref(cfg)))
+        return cfg.as_dict()
+
+    def set_config(self, config: dict, stream=None) -> None:
+        cfg = BatchConfig(**{k: int(v) for k, v in config.items()})
+        _check(load().lbmletkf_batch_set_config(self.handle, ctypes.byref(cfg), _stream(stream)))
+
+    def tune(self, reps: int = 3, stream=None) -> Tuple[dict, float, float]:
+        cfg = BatchConfig()
+        fms, ams = _c_double(), _c_double()
+        _check(load().lbmletkf_batch_tune(self.handle, int(reps), ctypes.byref(cfg),
+                                          ctypes.byref(fms), ctypes.byref(ams), _stream(stream)))
+        return cfg.as_dict(), fms.value, ams.value
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.lbmletkf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

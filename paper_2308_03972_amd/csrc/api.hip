@@ -294,6 +294,30 @@ void release_streams(Ctx* c) {
 }
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The analysis parameters of a context for the state d_f.
+AnalysisParams make_params(const Ctx* c, void* d_f) {
+    AnalysisParams p{};
+    p.f = d_f;
+    p.storage = c->storage();
+    p.nx = c->dims.nx;
+    p.ny = c->dims.ny;
+    p.members = c->dims.members;
+    p.dY = c->dY();
+    p.K = c->K();
+    p.dvec = c->dvec();
+    p.loc_pt = c->loc_pt();
+    p.loc_g = c->loc_g();
+    p.lmax = c->lmax;
+    p.nvar = c->obs.nvar;
+    p.nobs = c->nobs;
+    for (int v = 0; v < 3; ++v)
+        p.rinv[v] = v < c->obs.nvar ? 1.0 / (c->obs.sigma[v] * c->obs.sigma[v]) : 0.0;
+    p.a = (c->dims.members - 1) / c->obs.beta;
+    p.sqrt_beta = std::sqrt(c->obs.beta);
+    p.eig_fail = c->counters() + 1;
+    return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -536,25 +560,7 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
                                         c->dvec(), c->K(), s);
         if (e != hipSuccess) return hip_fail(e, "obs_stats");
     }
-    AnalysisParams p{};
-    p.f = d_f;
-    p.storage = c->storage();
-    p.nx = c->dims.nx;
-    p.ny = c->dims.ny;
-    p.members = c->dims.members;
-    p.dY = c->dY();
-    p.K = c->K();
-    p.dvec = c->dvec();
-    p.loc_pt = c->loc_pt();
-    p.loc_g = c->loc_g();
-    p.lmax = c->lmax;
-    p.nvar = c->obs.nvar;
-    p.nobs = c->nobs;
-    for (int v = 0; v < 3; ++v)
-        p.rinv[v] = v < c->obs.nvar ? 1.0 / (c->obs.sigma[v] * c->obs.sigma[v]) : 0.0;
-    p.a = (c->dims.members - 1) / c->obs.beta;
-    p.sqrt_beta = std::sqrt(c->obs.beta);
-    p.eig_fail = c->counters() + 1;
+    const AnalysisParams p = make_params(c, d_f);
     StageTimer t(c, kStageAnalysis, s);
     hipError_t e = hipSuccess;
     if (c->route == LBMLETKF_ROUTE_OBSERVATION) {
@@ -824,6 +830,552 @@ lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts)
     }
     c->recs.clear();
     return st;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batching form: many independent problems (contexts) per cycle.
+// ===========================================================================
+namespace {
+
+// Smallest instantiated observation-route size >= n that is a multiple of g.
+int coarse_size(int n, int g) {
+    int v = obs_size_for(n);
+    while (v != 0 && v % g != 0) v = obs_size_for(v + 1);
+    return v;
+}
+
+struct BatchGroup {
+    int route;  // LBMLETKF_ROUTE_ENSEMBLE or LBMLETKF_ROUTE_OBSERVATION
+    int n;      // eigenproblem size
+    int stream; // 0: the launch stream, k > 0: side stream k - 1
+    int4* eig_waves = nullptr;
+    int n_eig = 0;
+    int2* waves = nullptr;  // apply waves (observation route) or node waves (ensemble route)
+    int n_waves = 0;
+    int* nodes = nullptr;
+    double* gbuf = nullptr;
+    int nz_max = 0;
+    double cost = 0.0;
+};
+
+struct Batch {
+    std::vector<Ctx*> ctx;
+    std::vector<void*> f;
+    int nsteps = 0;
+    int storage = 0;
+    lbmletkf_batch_config cfg{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    AnalysisParams* d_params = nullptr;       // [n], f = the bound states
+    AnalysisParams* d_params_tune = nullptr;  // [n], f = the ping-pong partners
+    LbmTask* d_tasks[3] = {nullptr, nullptr, nullptr};  // even, odd, tuning steps
+    double* d_yo = nullptr;
+    std::vector<size_t> yo_off;
+    char* gbase = nullptr;  // group region
+    size_t gcap = 0;
+    std::vector<BatchGroup> groups;
+    int ntiles = 0;
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+    hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+Batch* as_batch(void* b) { return reinterpret_cast<Batch*>(b); }
+
+struct BatchLayout {
+    size_t params, params_tune, tasks, yo, groups, total, group_bytes;
+};
+
+BatchLayout batch_layout(const std::vector<Ctx*>& ctx) {
+    BatchLayout L{};
+    const size_t n = ctx.size();
+    size_t nobs = 0, nodes = 0, gdoubles = 0;
+    for (const Ctx* c : ctx) {
+        nobs += c->nobs;
+        const size_t plane = (size_t)c->dims.nx * c->dims.ny;
+        nodes += plane;
+        if (c->route == LBMLETKF_ROUTE_OBSERVATION)
+            for (const Bucket& b : c->buckets) {
+                const int nc = coarse_size(b.n, 8);  // the largest size any granularity gives
+                gdoubles += obs_gbuf_doubles(nc, b.count);
+            }
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.params = take(n * sizeof(AnalysisParams));
+    L.params_tune = take(n * sizeof(AnalysisParams));
+    L.tasks = take(3 * n * sizeof(LbmTask));
+    L.yo = take(nobs * sizeof(double));
+    // groups: node lists, eigen waves, apply/ensemble waves, G buffers (+ alignment slack
+    // for up to 64 groups of four arrays)
+    L.group_bytes = nodes * (sizeof(int) + sizeof(int4) + sizeof(int2)) + gdoubles * sizeof(double) +
+                    64 * 4 * kAlign;
+    L.groups = take(L.group_bytes);
+    L.total = off;
+    return L;
+}
+
+void batch_release(Batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (int k = 0; k < Batch::kSide; ++k) {
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+// Forecast tasks for the tile configuration: even steps f -> partner, odd steps
+// partner -> f, tuning steps f -> partner (the bound states stay untouched).
+lbmletkf_status batch_tasks(Batch* b, hipStream_t s) {
+    const int n = (int)b->ctx.size();
+    std::vector<LbmTask> t(3 * n);
+    int tile0 = 0;
+    for (int k = 0; k < n; ++k) {
+        const Ctx* c = b->ctx[k];
+        const int M = c->dims.members;
+        const int tile_nodes = b->cfg.tile_rows * (256 / M);
+        const int plane = c->dims.nx * c->dims.ny;
+        for (int v = 0; v < 3; ++v) {
+            LbmTask& x = t[v * n + k];
+            x.fin = v == 1 ? c->fbuf() : b->f[k];
+            x.fout = v == 1 ? b->f[k] : c->fbuf();
+            x.force = c->force();
+            x.nx = c->dims.nx;
+            x.ny = c->dims.ny;
+            x.members = M;
+            x.tile_nodes = tile_nodes;
+            x.tile0 = tile0;
+            x.tau0 = c->lbm.tau0;
+            x.smag = 18.0 * std::sqrt(2.0) * c->lbm.cs * c->lbm.cs;
+            x.mu = c->lbm.mu;
+        }
+        tile0 += (plane + tile_nodes - 1) / tile_nodes;
+    }
+    b->ntiles = tile0;
+    hipError_t e = hipMemcpyAsync(b->d_tasks[0], t.data(), t.size() * sizeof(LbmTask),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "batch tasks");
+}
+
+// Analysis groups for the bucket granularity: one group per (route, size) across problems.
+lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
+    const int n = (int)b->ctx.size();
+    const int g = b->cfg.bucket_granularity;
+    struct Range { int k, offset, count; };
+    std::vector<std::vector<Range>> obs(65);
+    std::vector<std::vector<int>> ens(65);
+    for (int k = 0; k < n; ++k) {
+        const Ctx* c = b->ctx[k];
+        if (c->route == LBMLETKF_ROUTE_OBSERVATION) {
+            for (const Bucket& bk : c->buckets)
+                if (bk.count > 0) obs[coarse_size(bk.n, g)].push_back({k, bk.offset, bk.count});
+        } else {
+            ens[c->n_eig].push_back(k);
+        }
+    }
+    b->groups.clear();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return b->gbase + at;
+    };
+    std::vector<std::vector<int4>> host_eig;
+    std::vector<std::vector<int2>> host_waves;
+    hipError_t e = hipSuccess;
+    for (int sz = 0; sz <= 64 && e == hipSuccess; ++sz) {
+        if (!obs[sz].empty()) {
+            BatchGroup grp;
+            grp.route = LBMLETKF_ROUTE_OBSERVATION;
+            grp.n = sz;
+            int total = 0;
+            for (const Range& r : obs[sz]) total += r.count;
+            grp.nodes = reinterpret_cast<int*>(take((size_t)total * sizeof(int)));
+            std::vector<int4> ew;
+            std::vector<int2> aw;
+            const int segs = obs_segments(sz);
+            int base = 0;
+            for (const Range& r : obs[sz]) {
+                e = hipMemcpyAsync(grp.nodes + base, b->ctx[r.k]->nodes() + r.offset,
+                                   (size_t)r.count * sizeof(int), hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) break;
+                for (int i = 0; i < r.count; i += segs) ew.push_back(make_int4(r.k, base + i, base + r.count, 0));
+                for (int i = 0; i < r.count; ++i) aw.push_back(make_int2(r.k, base + i));
+                grp.cost += (double)r.count * ((double)sz * sz * sz + 3000.0);
+                base += r.count;
+            }
+            grp.n_eig = (int)ew.size();
+            grp.n_waves = (int)aw.size();
+            grp.eig_waves = reinterpret_cast<int4*>(take(ew.size() * sizeof(int4)));
+            grp.waves = reinterpret_cast<int2*>(take(aw.size() * sizeof(int2)));
+            grp.gbuf = reinterpret_cast<double*>(take(obs_gbuf_doubles(sz, total) * sizeof(double)));
+            host_eig.push_back(std::move(ew));
+            host_waves.push_back(std::move(aw));
+            b->groups.push_back(grp);
+        }
+        if (!ens[sz].empty()) {
+            BatchGroup grp;
+            grp.route = LBMLETKF_ROUTE_ENSEMBLE;
+            grp.n = sz;
+            std::vector<int2> w;
+            for (int k : ens[sz]) {
+                const Ctx* c = b->ctx[k];
+                const int plane = c->dims.nx * c->dims.ny;
+                for (int i = 0; i < plane; ++i) w.push_back(make_int2(k, i));
+                grp.nz_max = std::max(grp.nz_max, c->obs.nvar * c->lmax);
+                grp.cost += (double)plane * 4.0 * sz * sz * sz;
+            }
+            grp.n_waves = (int)w.size();
+            grp.waves = reinterpret_cast<int2*>(take(w.size() * sizeof(int2)));
+            host_eig.emplace_back();
+            host_waves.push_back(std::move(w));
+            b->groups.push_back(grp);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch node lists");
+    if (off > b->gcap) return fail(LBMLETKF_EWORKSPACE, "batch workspace too small for its groups");
+    for (size_t i = 0; i < b->groups.size() && e == hipSuccess; ++i) {
+        BatchGroup& grp = b->groups[i];
+        if (!host_eig[i].empty())
+            e = hipMemcpyAsync(grp.eig_waves, host_eig[i].data(), host_eig[i].size() * sizeof(int4),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !host_waves[i].empty())
+            e = hipMemcpyAsync(grp.waves, host_waves[i].data(), host_waves[i].size() * sizeof(int2),
+                               hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch waves");
+    // longest processing time first over the launch stream and the side streams
+    std::vector<int> order(b->groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->groups[x].cost > b->groups[y].cost; });
+    double load[1 + Batch::kSide] = {0.0, 0.0, 0.0, 0.0};
+    for (int i : order) {
+        int best = 0;
+        for (int k = 1; k <= Batch::kSide; ++k)
+            if (load[k] < load[best]) best = k;
+        b->groups[i].stream = best;
+        load[best] += b->groups[i].cost;
+    }
+    std::vector<BatchGroup> sorted;
+    for (int i : order) sorted.push_back(b->groups[i]);
+    b->groups.swap(sorted);
+    return LBMLETKF_OK;
+}
+
+// The analyses of all problems (statistics already done), forked over the streams.
+hipError_t batch_analysis(Batch* b, const AnalysisParams* params, hipStream_t s) {
+    bool used[Batch::kSide] = {false, false, false};
+    for (const BatchGroup& grp : b->groups)
+        if (grp.stream > 0) used[grp.stream - 1] = true;
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (int k = 0; k < Batch::kSide && e == hipSuccess; ++k)
+        if (used[k]) e = hipStreamWaitEvent(b->side[k], b->fork, 0);
+    for (const BatchGroup& grp : b->groups) {
+        if (e != hipSuccess) break;
+        hipStream_t sk = grp.stream == 0 ? s : b->side[grp.stream - 1];
+        if (grp.route == LBMLETKF_ROUTE_OBSERVATION)
+            e = launch_analysis_obs_batch(params, grp.eig_waves, grp.n_eig, grp.waves, grp.n_waves,
+                                          grp.nodes, grp.n, grp.gbuf, b->storage, sk);
+        else
+            e = launch_analysis_ens_batch(params, grp.waves, grp.n_waves, grp.n, grp.nz_max,
+                                          b->storage, sk);
+    }
+    for (int k = 0; k < Batch::kSide && e == hipSuccess; ++k) {
+        if (!used[k]) continue;
+        e = hipEventRecord(b->join[k], b->side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[k], 0);
+    }
+    return e;
+}
+
+// Observation operator and statistics of every problem (inputs: the bound states
+// or, for tuning, their partners).
+hipError_t batch_observe(Batch* b, bool partners, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < b->ctx.size() && e == hipSuccess; ++k) {
+        Ctx* c = b->ctx[k];
+        const void* f = partners ? c->fbuf() : b->f[k];
+        e = launch_observe(f, c->pts(), c->obs.n_points, c->obs.nvar, c->yf(), c->dims,
+                           b->storage, s);
+        if (e == hipSuccess)
+            e = launch_obs_stats(c->yf(), b->d_yo + b->yo_off[k], c->nobs, c->dims.members,
+                                 c->ybar(), c->dY(), c->dvec(), c->K(), s);
+    }
+    return e;
+}
+
+// One whole cycle of every problem on stream s.
+hipError_t batch_issue_cycle(Batch* b, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const int n = (int)b->ctx.size();
+    for (int step = 0; step < b->nsteps && e == hipSuccess; ++step)
+        e = launch_stream_collide_batch(b->d_tasks[step & 1], n, b->ntiles,
+                                        b->cfg.forecast_blocks, b->storage, s);
+    if (b->nsteps & 1)
+        for (int k = 0; k < n && e == hipSuccess; ++k)
+            e = hipMemcpyAsync(b->f[k], b->ctx[k]->fbuf(), b->ctx[k]->state_bytes(),
+                               hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = batch_observe(b, false, s);
+    if (e == hipSuccess) e = batch_analysis(b, b->d_params, s);
+    return e;
+}
+
+lbmletkf_status batch_capture(Batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (!b->cfg.use_graph) return LBMLETKF_OK;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "batch capture");
+    hipError_t e2 = batch_issue_cycle(b, b->cap);
+    e = hipStreamEndCapture(b->cap, &b->graph);
+    if (e2 != hipSuccess) return hip_fail(e2, "batch capture launches");
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "batch graph");
+}
+
+lbmletkf_status batch_check_config(const lbmletkf_batch_config* cfg) {
+    if (cfg->forecast_blocks < 1 || cfg->forecast_blocks > (1 << 20))
+        return fail(LBMLETKF_EINVAL, "forecast_blocks must be in 1..2^20");
+    if (cfg->tile_rows < 1 || cfg->tile_rows > 64)
+        return fail(LBMLETKF_EINVAL, "tile_rows must be in 1..64");
+    if (cfg->bucket_granularity != 2 && cfg->bucket_granularity != 4 &&
+        cfg->bucket_granularity != 8)
+        return fail(LBMLETKF_EINVAL, "bucket_granularity must be 2, 4 or 8");
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status batch_apply_config(Batch* b, const lbmletkf_batch_config* cfg, hipStream_t s) {
+    lbmletkf_status st = batch_check_config(cfg);
+    if (st) return st;
+    b->cfg = *cfg;
+    if ((st = batch_tasks(b, s))) return st;
+    if ((st = batch_groups(b, s))) return st;
+    return batch_capture(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmletkf_status lbmletkf_batch_workspace_bytes(void* const* ctxs, int32_t n, size_t* bytes) {
+    if (!ctxs || n < 1 || !bytes) return fail(LBMLETKF_EINVAL, "need n >= 1 contexts and bytes");
+    std::vector<Ctx*> v;
+    for (int k = 0; k < n; ++k) {
+        if (!ctxs[k]) return fail(LBMLETKF_EINVAL, "NULL context");
+        v.push_back(as_ctx(ctxs[k]));
+    }
+    *bytes = batch_layout(v).total;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32_t n,
+                                      int32_t nsteps, const lbmletkf_batch_config* cfg,
+                                      void* d_workspace, size_t bytes, void* stream,
+                                      void** batch_out) {
+    if (!ctxs || !d_f || n < 1 || !batch_out) return fail(LBMLETKF_EINVAL, "NULL argument");
+    *batch_out = nullptr;
+    if (nsteps < 1) return fail(LBMLETKF_EINVAL, "nsteps must be >= 1");
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
+        return fail(LBMLETKF_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    lbmletkf_batch_config c0{256 * 4, 1, 2, 1};
+    const lbmletkf_batch_config* use = cfg ? cfg : &c0;
+    lbmletkf_status st = batch_check_config(use);
+    if (st) return st;
+    std::vector<Ctx*> v;
+    for (int k = 0; k < n; ++k) {
+        if (!ctxs[k] || !d_f[k]) return fail(LBMLETKF_EINVAL, "NULL context or state");
+        Ctx* c = as_ctx(ctxs[k]);
+        if (256 % c->dims.members != 0)
+            return fail(LBMLETKF_EUNSUPPORTED, "batched members must divide 256");
+        if (k > 0 && c->storage() != v[0]->storage())
+            return fail(LBMLETKF_EUNSUPPORTED, "every problem of a batch needs the same storage");
+        for (void* g : std::vector<void*>(d_f, d_f + k))
+            if (g == d_f[k]) return fail(LBMLETKF_EINVAL, "two problems share a state buffer");
+        v.push_back(c);
+    }
+    const BatchLayout L = batch_layout(v);
+    if (bytes < L.total) return fail(LBMLETKF_EWORKSPACE, "batch workspace too small");
+    Batch* b = new Batch();
+    b->ctx = v;
+    b->f.assign(d_f, d_f + n);
+    b->nsteps = nsteps;
+    b->storage = v[0]->storage();
+    b->ws = reinterpret_cast<char*>(d_workspace);
+    b->ws_bytes = bytes;
+    b->d_params = reinterpret_cast<AnalysisParams*>(b->ws + L.params);
+    b->d_params_tune = reinterpret_cast<AnalysisParams*>(b->ws + L.params_tune);
+    b->d_tasks[0] = reinterpret_cast<LbmTask*>(b->ws + L.tasks);
+    b->d_tasks[1] = b->d_tasks[0] + n;
+    b->d_tasks[2] = b->d_tasks[0] + 2 * n;
+    b->d_yo = reinterpret_cast<double*>(b->ws + L.yo);
+    b->gbase = b->ws + L.groups;
+    b->gcap = L.group_bytes;
+    size_t yo = 0;
+    for (Ctx* c : v) {
+        b->yo_off.push_back(yo);
+        yo += c->nobs;
+    }
+    hipStream_t s = as_stream(stream);
+    std::vector<AnalysisParams> p(2 * n);
+    for (int k = 0; k < n; ++k) {
+        p[k] = make_params(v[k], d_f[k]);
+        p[n + k] = make_params(v[k], v[k]->fbuf());
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int k = 0; k < Batch::kSide && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_params, p.data(), 2 * n * sizeof(AnalysisParams),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        batch_release(b);
+        delete b;
+        return hip_fail(e, "lbmletkf_batch_create");
+    }
+    if ((st = batch_apply_config(b, use, s))) {
+        batch_release(b);
+        delete b;
+        return st;
+    }
+    *batch_out = b;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_batch_destroy(void* batch) {
+    Batch* b = as_batch(batch);
+    if (!b) return fail(LBMLETKF_EINVAL, "batch is NULL");
+    batch_release(b);
+    delete b;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_batch_run_cycle(void* batch, const double* const* d_yo, void* stream) {
+    Batch* b = as_batch(batch);
+    if (!b || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < b->ctx.size() && e == hipSuccess; ++k) {
+        if (!d_yo[k]) return fail(LBMLETKF_EINVAL, "NULL observation vector");
+        e = hipMemcpyAsync(b->d_yo + b->yo_off[k], d_yo[k], b->ctx[k]->nobs * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess) e = b->exec ? hipGraphLaunch(b->exec, s) : batch_issue_cycle(b, s);
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "batch cycle");
+}
+
+lbmletkf_status lbmletkf_batch_get_config(void* batch, lbmletkf_batch_config* cfg) {
+    Batch* b = as_batch(batch);
+    if (!b || !cfg) return fail(LBMLETKF_EINVAL, "NULL argument");
+    *cfg = b->cfg;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_batch_set_config(void* batch, const lbmletkf_batch_config* cfg,
+                                          void* stream) {
+    Batch* b = as_batch(batch);
+    if (!b || !cfg) return fail(LBMLETKF_EINVAL, "NULL argument");
+    return batch_apply_config(b, cfg, as_stream(stream));
+}
+
+lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_config* best,
+                                    double* forecast_ms, double* analysis_ms, void* stream) {
+    Batch* b = as_batch(batch);
+    if (!b || reps < 1) return fail(LBMLETKF_EINVAL, "need a batch and reps >= 1");
+    hipStream_t s = as_stream(stream);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    auto timed = [&](auto&& body, double* ms) -> hipError_t {
+        hipError_t r = body();  // warm-up (and first-use setup)
+        if (r == hipSuccess) r = hipEventRecord(t0, s);
+        for (int i = 0; i < reps && r == hipSuccess; ++i) r = body();
+        if (r == hipSuccess) r = hipEventRecord(t1, s);
+        if (r == hipSuccess) r = hipEventSynchronize(t1);
+        float t = 0.0f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&t, t0, t1);
+        *ms = t / reps;
+        return r;
+    };
+    lbmletkf_batch_config cur = b->cfg;
+    cur.use_graph = 0;
+    lbmletkf_batch_config best_cfg = cur;
+    double best_f = 1e30, best_a = 1e30;
+    lbmletkf_status st = LBMLETKF_OK;
+    // forecast: persistent blocks x tile rows, stepping the bound states into their
+    // partners (the bound states are not modified)
+    const int blocks[] = {256, 512, 1024, 2048};
+    const int rows[] = {1, 2, 4, 8};
+    for (int bl : blocks) {
+        for (int tr : rows) {
+            if (e != hipSuccess || st) break;
+            cur.forecast_blocks = bl;
+            cur.tile_rows = tr;
+            b->cfg = cur;
+            if ((st = batch_tasks(b, s))) break;
+            double ms = 0.0;
+            e = timed([&]() {
+                return launch_stream_collide_batch(b->d_tasks[2], (int)b->ctx.size(), b->ntiles,
+                                                   bl, b->storage, s);
+            }, &ms);
+            if (e == hipSuccess && ms < best_f) {
+                best_f = ms;
+                best_cfg.forecast_blocks = bl;
+                best_cfg.tile_rows = tr;
+            }
+        }
+    }
+    // analysis: bucket granularity, on copies of the states in the partner buffers
+    for (size_t k = 0; k < b->ctx.size() && e == hipSuccess && !st; ++k)
+        e = hipMemcpyAsync(b->ctx[k]->fbuf(), b->f[k], b->ctx[k]->state_bytes(),
+                           hipMemcpyDeviceToDevice, s);
+    const int grans[] = {2, 4, 8};
+    for (int g : grans) {
+        if (e != hipSuccess || st) break;
+        cur = best_cfg;
+        cur.bucket_granularity = g;
+        b->cfg = cur;
+        if ((st = batch_groups(b, s))) break;
+        double ms = 0.0;
+        e = batch_observe(b, true, s);
+        if (e == hipSuccess) e = timed([&]() { return batch_analysis(b, b->d_params_tune, s); }, &ms);
+        if (e == hipSuccess && ms < best_a) {
+            best_a = ms;
+            best_cfg.bucket_granularity = g;
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "batch tune");
+    if (st) return st;
+    best_cfg.use_graph = 1;
+    if ((st = batch_apply_config(b, &best_cfg, s))) return st;
+    if (best) *best = best_cfg;
+    if (forecast_ms) *forecast_ms = best_f;
+    if (analysis_ms) *analysis_ms = best_a;
+    return LBMLETKF_OK;
 }
 
 }  // extern "C"

@@ -83,6 +83,20 @@ struct LbmDims {
 // `storage` selects the element type of every state buffer (Storage).
 hipError_t launch_stream_collide(const void* fin, void* fout, const double* force, LbmDims d,
                                  double tau0, double cs, double mu, int storage, hipStream_t s);
+// One problem of a batched forecast step: its state buffers (storage layout),
+// force, sizes, relaxation parameters and its first tile in the batch.
+struct LbmTask {
+    const void* fin;
+    void* fout;
+    const double* force;
+    int nx, ny, members;  // members divides 256
+    int tile_nodes;       // nodes per tile (a multiple of 256 / members)
+    int tile0;            // first tile of this problem in the concatenated list
+    double tau0, smag, mu;
+};
+// All problems' steps in one persistent launch of `blocks` blocks over `ntiles` tiles.
+hipError_t launch_stream_collide_batch(const LbmTask* d_tasks, int ntasks, int ntiles, int blocks,
+                                       int storage, hipStream_t s);
 hipError_t launch_import(const double* canon, void* f, LbmDims d, int storage, hipStream_t s);
 hipError_t launch_export(const void* f, double* canon, LbmDims d, int storage, hipStream_t s);
 hipError_t launch_init_equilibrium(const double* rho, const double* uv, void* f, LbmDims d,
@@ -116,6 +130,10 @@ struct AnalysisParams {
 hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s);
 int ens_size_for(int n);              // instantiated size >= n, or 0
 int ens_lds_bytes(int n, int nz);
+// Batched ensemble route: wavefront w handles waves[w] = (problem, node); nz_max
+// is the largest nvar * lmax among the problems.
+hipError_t launch_analysis_ens_batch(const AnalysisParams* d_params, const int2* d_waves,
+                                     int nwaves, int n, int nz_max, int storage, hipStream_t s);
 // Observation route (l x l dual, size n >= l) for the `count` nodes listed in
 // `nodes`; gbuf holds obs_gbuf_doubles(n, count) doubles (per-node G and h
 // passed from the eigen kernel to the apply kernel).
@@ -124,6 +142,16 @@ hipError_t launch_analysis_obs(const AnalysisParams& p, const int* nodes, int co
 int obs_size_for(int n);              // instantiated size >= n, or 0
 int obs_lds_bytes(int n);             // the larger of the two kernels' LDS
 size_t obs_gbuf_doubles(int n, int count);
+int obs_segments(int n);              // nodes per wavefront of the eigen kernel
+// Batched observation route for one eigenproblem size n over many problems:
+// eigen wavefront w handles eig_waves[w] = (problem, first item, end of that
+// problem's items, -); apply wavefront w handles apply_waves[w] = (problem, item);
+// items index the shared node list and G buffer; d_params[problem] is that
+// problem's AnalysisParams.
+hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4* d_eig_waves,
+                                     int n_eig, const int2* d_apply_waves, int n_apply,
+                                     const int* d_nodes, int n, double* gbuf, int storage,
+                                     hipStream_t s);
 int diag_blocks_for(int plane);
 
 hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int storage,

@@ -57,14 +57,13 @@ __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double
     }
 }
 
+// Pull, collide and store one (node, member).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void stream_collide_kernel(
-    const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
-    int ny, int members, double tau0, double smag, double mu) {
+__device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restrict__ fout,
+                                           const double* __restrict__ force, int nx, int ny,
+                                           int members, int node, int m, double tau0,
+                                           double smag, double mu) {
     const int plane = nx * ny;
-    const int m = threadIdx.x;  // blockDim.x == members
-    const int node = blockIdx.x * blockDim.y + threadIdx.y;
-    if (node >= plane) return;
     const int y = node / nx, x = node - y * nx;
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
@@ -85,6 +84,42 @@ __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
     collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
     for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void stream_collide_kernel(
+    const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
+    int ny, int members, double tau0, double smag, double mu) {
+    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    if (node >= nx * ny) return;
+    lbm_update<T>(fin, fout, force, nx, ny, members, node, threadIdx.x, tau0, smag, mu);
+}
+
+// Many problems in one persistent launch: blocks of 256 threads walk the
+// concatenated tile list (problem k owns tiles [tile0_k, tile0_{k+1})); a
+// tile is `tile_nodes` consecutive nodes of one problem, processed as rows of
+// (256 / M) nodes x M members.  The schedule is static (block b takes tiles
+// b, b + gridDim.x, ...), so every launch does the same work in the same order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void stream_collide_batch_kernel(const LbmTask* __restrict__ tasks,
+                                                                      int ntasks, int ntiles) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int k = 0;
+        while (k + 1 < ntasks && tasks[k + 1].tile0 <= t) ++k;
+        const LbmTask& tk = tasks[k];
+        const int M = tk.members;
+        const int npb = kBlock / M;
+        const int plane = tk.nx * tk.ny;
+        const int node0 = (t - tk.tile0) * tk.tile_nodes;
+        const int m = threadIdx.x % M, nl = threadIdx.x / M;
+        if (nl >= npb) continue;
+        for (int r = nl; r < tk.tile_nodes; r += npb) {
+            const int node = node0 + r;
+            if (node >= plane) break;
+            lbm_update<T>(static_cast<const T*>(tk.fin), static_cast<T*>(tk.fout), tk.force, tk.nx,
+                          tk.ny, M, node, m, tk.tau0, tk.smag, tk.mu);
+        }
+    }
 }
 
 // storage slot (node (x, y), a, m) <- canonical [m][a][y + c_ay][x + c_ax]
@@ -191,6 +226,15 @@ hipError_t launch_stream_collide(const void* fin, void* fout, const double* forc
     else
         stream_collide_kernel<double><<<grid, block, 0, s>>>(
             (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_collide_batch(const LbmTask* d_tasks, int ntasks, int ntiles, int blocks,
+                                       int storage, hipStream_t s) {
+    if (storage == kStoreF32Dev)
+        stream_collide_batch_kernel<float><<<blocks, kBlock, 0, s>>>(d_tasks, ntasks, ntiles);
+    else
+        stream_collide_batch_kernel<double><<<blocks, kBlock, 0, s>>>(d_tasks, ntasks, ntiles);
     return hipGetLastError();
 }
 

@@ -111,7 +111,9 @@ __global__ void local_table_kernel(const int* __restrict__ pts, int npts, double
             g = 1.0;
         } else {
             if (!(r2 < lim)) continue;
-            g = gaspari_cohn(sqrt(r2) / d_cut);
+            // the polynomial vanishes at d = 2 d_cut; just inside, its rounding can
+            // fall ~1e-16 below zero: the weight is kept non-negative
+            g = fmax(gaspari_cohn(sqrt(r2) / d_cut), 0.0);
         }
         if (cnt < lmax) {
             loc_pt[(size_t)node * lmax + cnt] = k;
@@ -137,15 +139,13 @@ __host__ __device__ inline int ens_lds_doubles(int n, int nz) {
     return 9 * 64 + n * rs + 4 * 64 + 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
 }
 
+// One wavefront: node `node` of one problem, lane = member.
 template <int N, typename T>
-__global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int max_sweeps) {
+__device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int max_sweeps) {
     T* __restrict__ fs = reinterpret_cast<T*>(p.f);
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int nx = p.nx, ny = p.ny, M = p.members;
-    const int plane = nx * ny;
-    const int node = xcd_remap(blockIdx.x, gridDim.x);
-    if (node >= plane) return;
     const int nz = p.nvar * p.lmax;
     const int nzp = (nz + 1) & ~1;
     double* sdx = lds;                   // [9][64]
@@ -243,6 +243,24 @@ __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int 
                             xbar[a] + dmean[a] + acc);
         }
     }
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int max_sweeps) {
+    const int node = xcd_remap(blockIdx.x, gridDim.x);
+    if (node >= p.nx * p.ny) return;
+    ens_body<N, T>(p, node, max_sweeps);
+}
+
+// Batched form: wavefront w takes waves[w] = (problem, node).
+template <int N, typename T>
+__global__ __launch_bounds__(64) void analysis_ens_batch_kernel(const AnalysisParams* P,
+                                                                const int2* waves, int nwaves,
+                                                                int max_sweeps) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= nwaves) return;
+    const int2 d = waves[w];
+    ens_body<N, T>(P[d.x], d.y, max_sweeps);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,7 +420,42 @@ hipError_t launch_ens_sized(const AnalysisParams& p, int n, hipStream_t s) {
     }
 }
 
+template <int N, typename T>
+hipError_t launch_ens_batch_t(const AnalysisParams* P, const int2* waves, int nwaves, int nz_max,
+                              hipStream_t s) {
+    if (nwaves == 0) return hipSuccess;
+    const size_t bytes = (size_t)ens_lds_doubles(N, nz_max) * sizeof(double);
+    if (bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)analysis_ens_batch_kernel<N, T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    analysis_ens_batch_kernel<N, T><<<nwaves, 64, bytes, s>>>(P, waves, nwaves, 30);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_ens_batch(const AnalysisParams* P, const int2* waves, int nwaves, int nz_max,
+                            int storage, hipStream_t s) {
+    return storage == kStoreF32Dev ? launch_ens_batch_t<N, float>(P, waves, nwaves, nz_max, s)
+                                   : launch_ens_batch_t<N, double>(P, waves, nwaves, nz_max, s);
+}
+
 }  // namespace
+
+hipError_t launch_analysis_ens_batch(const AnalysisParams* d_params, const int2* d_waves,
+                                     int nwaves, int n, int nz_max, int storage, hipStream_t s) {
+    switch (n) {
+        case 8: return launch_ens_batch<8>(d_params, d_waves, nwaves, nz_max, storage, s);
+        case 16: return launch_ens_batch<16>(d_params, d_waves, nwaves, nz_max, storage, s);
+        case 24: return launch_ens_batch<24>(d_params, d_waves, nwaves, nz_max, storage, s);
+        case 32: return launch_ens_batch<32>(d_params, d_waves, nwaves, nz_max, storage, s);
+        case 48: return launch_ens_batch<48>(d_params, d_waves, nwaves, nz_max, storage, s);
+        case 64: return launch_ens_batch<64>(d_params, d_waves, nwaves, nz_max, storage, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 int ens_size_for(int n) {
     const int sizes[] = {8, 16, 24, 32, 48, 64};

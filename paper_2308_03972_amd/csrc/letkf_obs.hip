@@ -58,10 +58,10 @@ __device__ __forceinline__ void local_obs(const AnalysisParams& p, int node, int
     if (d) *d = *w * p.dvec[*q];
 }
 
+// One wavefront: the nodes nodes[item0 + seg] (seg < SEGS, item < end) of one problem.
 template <int N>
-__global__ __launch_bounds__(64) void analysis_eig_kernel(AnalysisParams p, const int* nodes,
-                                                          int count, double* gout,
-                                                          int max_sweeps) {
+__device__ __forceinline__ void eig_body(const AnalysisParams p, const int* nodes, int item0,
+                                         int end, double* gout, int max_sweeps) {
     using L = EigLayout<N>;
     constexpr int SEGS = L::SEGS;
     constexpr int RS = L::RS;
@@ -80,8 +80,8 @@ __global__ __launch_bounds__(64) void analysis_eig_kernel(AnalysisParams p, cons
     const int i = lane - seg * N;
     const bool active = seg < SEGS;
     const int sbase = active ? seg * N : 0;
-    const int item = xcd_remap(blockIdx.x, gridDim.x) * SEGS + (active ? seg : 0);
-    const bool valid = active && item < count;
+    const int item = item0 + (active ? seg : 0);
+    const bool valid = active && item < end;
     const int node = valid ? nodes[item] : 0;
 
     if (active) {
@@ -153,6 +153,32 @@ __global__ __launch_bounds__(64) void analysis_eig_kernel(AnalysisParams p, cons
     }
 }
 
+// Up to N = 18 the eigensolver fits in 168 VGPRs (three wavefronts per SIMD)
+// without spilling; larger N keep the compiler's choice.
+template <int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
+void analysis_eig_kernel(AnalysisParams p, const int* nodes,
+                                                          int count, double* gout,
+                                                          int max_sweeps) {
+    eig_body<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x) * EigLayout<N>::SEGS, count, gout,
+                max_sweeps);
+}
+
+// Batched form: wavefront w takes waves[w] = (problem, first item, end of the
+// problem's items); the items of all problems share one node list and one G buffer.
+template <int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
+void analysis_eig_batch_kernel(const AnalysisParams* P,
+                                                                const int4* waves, int nwaves,
+                                                                const int* nodes, double* gout,
+                                                                int max_sweeps) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= nwaves) return;
+    const int4 d = waves[w];
+    const AnalysisParams p = P[d.x];
+    eig_body<N>(p, nodes, d.y, d.z, gout, max_sweeps);
+}
+
 // ---------------------------------------------------------------------------
 // apply part: one node per wavefront, lane = member
 // ---------------------------------------------------------------------------
@@ -162,10 +188,10 @@ __host__ __device__ inline int apply_lds_doubles(int n) {
     return n * n + n + 9 * 64 + 9 * n + 10 * n + n + 9 + 9 + (n + 1) / 2;
 }
 
+// One wavefront: node nodes[item] of one problem, lane = member.
 template <int N, typename T>
-__global__ __launch_bounds__(64) void analysis_apply_kernel(AnalysisParams p, const int* nodes,
-                                                            int count,
-                                                            const double* __restrict__ gin) {
+__device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* nodes, int item,
+                                           const double* __restrict__ gin) {
     constexpr int n = N;
     constexpr int groups = kWave / N;                  // member groups in B
     constexpr int kChunk = (kWave + groups - 1) / groups;
@@ -182,8 +208,6 @@ __global__ __launch_bounds__(64) void analysis_apply_kernel(AnalysisParams p, co
     int* qx = reinterpret_cast<int*>(xbv + 9);         // [n]
 
     const int lane = threadIdx.x;
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
-    if (item >= count) return;                         // uniform over the wavefront
     const int node = nodes[item];
     const int nx = p.nx, ny = p.ny, M = p.members;
     const bool mem = lane < M;
@@ -299,6 +323,28 @@ __global__ __launch_bounds__(64) void analysis_apply_kernel(AnalysisParams p, co
     }
 }
 
+template <int N, typename T>
+__global__ __launch_bounds__(64) void analysis_apply_kernel(AnalysisParams p, const int* nodes,
+                                                            int count,
+                                                            const double* __restrict__ gin) {
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= count) return;  // uniform over the wavefront
+    apply_body<N, T>(p, nodes, item, gin);
+}
+
+// Batched form: wavefront w takes waves[w] = (problem, item).
+template <int N, typename T>
+__global__ __launch_bounds__(64) void analysis_apply_batch_kernel(const AnalysisParams* P,
+                                                                  const int2* waves, int nwaves,
+                                                                  const int* nodes,
+                                                                  const double* __restrict__ gin) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= nwaves) return;
+    const int2 d = waves[w];
+    const AnalysisParams p = P[d.x];
+    apply_body<N, T>(p, nodes, d.y, gin);
+}
+
 template <int N>
 hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double* gbuf,
                     hipStream_t s) {
@@ -314,6 +360,26 @@ hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double
         analysis_apply_kernel<N, float><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
     else
         analysis_apply_kernel<N, double><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_batch_n(const AnalysisParams* d_params, const int4* d_eig_waves, int n_eig,
+                          const int2* d_apply_waves, int n_apply, const int* d_nodes,
+                          double* gbuf, int storage, hipStream_t s) {
+    using L = EigLayout<N>;
+    if (n_eig == 0) return hipSuccess;
+    analysis_eig_batch_kernel<N><<<n_eig, 64, (size_t)L::total * sizeof(double), s>>>(
+        d_params, d_eig_waves, n_eig, d_nodes, gbuf, 30);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
+    if (storage == kStoreF32Dev)
+        analysis_apply_batch_kernel<N, float><<<n_apply, 64, app_bytes, s>>>(
+            d_params, d_apply_waves, n_apply, d_nodes, gbuf);
+    else
+        analysis_apply_batch_kernel<N, double><<<n_apply, 64, app_bytes, s>>>(
+            d_params, d_apply_waves, n_apply, d_nodes, gbuf);
     return hipGetLastError();
 }
 
@@ -350,6 +416,23 @@ hipError_t launch_analysis_obs(const AnalysisParams& p, const int* nodes, int co
                                double* gbuf, hipStream_t s) {
     switch (n) {
 #define X(v) case v: return launch_n<v>(p, nodes, count, gbuf, s);
+        LBMLETKF_OBS_SIZES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int obs_segments(int n) { return n > 0 ? 64 / n : 0; }
+
+hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4* d_eig_waves,
+                                     int n_eig, const int2* d_apply_waves, int n_apply,
+                                     const int* d_nodes, int n, double* gbuf, int storage,
+                                     hipStream_t s) {
+    switch (n) {
+#define X(v)                                                                                   \
+    case v:                                                                                    \
+        return launch_batch_n<v>(d_params, d_eig_waves, n_eig, d_apply_waves, n_apply, d_nodes, \
+                                 gbuf, storage, s);
         LBMLETKF_OBS_SIZES(X)
 #undef X
         default: return hipErrorInvalidValue;

@@ -150,6 +150,25 @@ CONFIGS: Dict[str, CycleConfig] = {
 }
 
 
+def batch_configs() -> List[CycleConfig]:
+    """The twelve problems of the batching form: grids {128, 192, 256, 384}^2 x
+    members {16, 32, 64}, problem i = 3 g + m (g grid index, m member index),
+    observation grid side [4, 8, 16, 32][(g + m) mod 4] and localization length
+    r = [0.15, 0.5, 0.73][(g + 2 m) mod 3] x the observation spacing, which gives
+    0-4, 16-24 and 32-44 local observations per node.  Every problem draws its
+    own fields (seed offset i); other parameters as the paper-scale configuration."""
+    base = CONFIGS["paper"]
+    out = []
+    for g, n in enumerate((128, 192, 256, 384)):
+        for m, members in enumerate((16, 32, 64)):
+            side = (4, 8, 16, 32)[(g + m) % 4]
+            ratio = (0.15, 0.5, 0.73)[(g + 2 * m) % 3]
+            out.append(base.replace(name=f"batch{3 * g + m}", n=n, members=members,
+                                    obs_side=side, loc_r=ratio * n / side,
+                                    seed=base.seed + 1 + 3 * g + m))
+    return out
+
+
 # --------------------------------------------------------------------------
 # random streams
 # --------------------------------------------------------------------------

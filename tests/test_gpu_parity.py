@@ -178,6 +178,20 @@ def test_analysis_member_counts(members):
         _check_analysis(got, ref, before)
 
 
+@pytest.mark.parametrize("route", [1, 2])
+def test_analysis_points_near_the_cutoff(route):
+    """64^2, 32 members (ensemble size 32), points 16 cells apart and d_cut =
+    20.23: some points lie at 40.46 cells, just inside 2 d_cut, where the
+    Gaspari-Cohn polynomial's rounding dips below zero (a regression test: the
+    weight must be clamped, not rooted into NaN)."""
+    say(f"analysis near the cutoff route={route}")
+    cfg = TINY.replace(n=64, members=32, obs_side=4, loc_r=11.68, seed=31)
+    ft, fe = config_state(cfg, spin_steps=3)
+    ctx, got, ref, before = _analysis_case(cfg, fe, ft, route)
+    assert np.isfinite(got).all()
+    _check_analysis(got, ref, before)
+
+
 def test_analysis_empty_neighbourhoods():
     """Small d_cut: nodes far from every point have l = 0 and only inflate."""
     say("analysis with empty neighbourhoods")
