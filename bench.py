@@ -178,6 +178,87 @@ def differentiation_form(reps: int, storage: int):
     }
 
 
+def batching_form(cycles: int, warmup: int):
+    """The twelve-problem batch (grids 128-384, 16-64 members, 0-44 local
+    observations, FP32 storage, s = 20): autotuned, cycle replayed from its
+    hipGraph, against the same problems run one after another through
+    run_cycle (no graph)."""
+    import torch
+    from paper_2308_03972_amd import binding, inputs
+    dev = torch.device("cuda:0")
+    cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    cfgs = inputs.batch_configs()
+    total = warmup + cycles
+    ctxs, mem, yos = [], [], []
+    for cfg in cfgs:
+        force = cuda(inputs.body_force(cfg))
+        ctx = binding.Context.from_config(cfg, force=force, storage=binding.STORAGE_F32_DEV)
+        tctx = binding.Context.from_config(cfg, members=1, force=force)
+        truth_uv, mem_uv = inputs.initial_velocities(cfg)
+        ft = tctx.init_equilibrium(cuda(truth_uv[None]))
+        noise = cuda(inputs.all_observation_noise(cfg, total))
+        sig = cuda(inputs.sigma_vector(cfg))
+        yo = []
+        for c in range(total):
+            tctx.step(ft, cfg.steps_per_cycle)
+            yo.append(binding.synth_obs(tctx.observe(ft)[0].contiguous(), noise[c].contiguous(),
+                                        sig))
+        ctxs.append(ctx)
+        mem.append(cuda(mem_uv))
+        yos.append(yo)
+    s = cfgs[0].steps_per_cycle
+    node_members = sum(c.n * c.n * c.members for c in cfgs)
+    # sequential: every problem through run_cycle, one after another
+    states = [c.init_equilibrium(m) for c, m in zip(ctxs, mem)]
+    for c in range(warmup):
+        for k, ctx in enumerate(ctxs):
+            ctx.run_cycle(states[k], s, yos[k][c])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(warmup, total):
+        for k, ctx in enumerate(ctxs):
+            ctx.run_cycle(states[k], s, yos[k][c])
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    seq_states = [st.clone() for st in states]
+    # batched, tuned, graph replay
+    states = [c.init_equilibrium(m) for c, m in zip(ctxs, mem)]
+    batch = binding.Batch(ctxs, states, s)
+    cfg_best, fms, ams = batch.tune(reps=3)
+    for c in range(warmup):
+        batch.run_cycle([yos[k][c] for k in range(len(cfgs))])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(warmup, total):
+        batch.run_cycle([yos[k][c] for k in range(len(cfgs))])
+    torch.cuda.synchronize()
+    bt = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(states, seq_states))
+    maxdiff = max(float((a.double() - b.double()).abs().max()) for a, b in zip(states, seq_states))
+    batch.close()
+    fc_bytes = 72.0 * node_members
+    gbs = fc_bytes / (fms * 1e-3) / 1e9
+    return {
+        "workload": ("12 problems: grids {128,192,256,384}^2 x members {16,32,64}, "
+                     "observation grids 4x4..32x32, 0-44 local observations, FP32 f - w, s=20"),
+        "node_members_per_step": node_members,
+        "cycles_per_s": round(cycles / bt, 3),
+        "glups_member": round(node_members * s * cycles / bt / 1e9, 3),
+        "sequential_cycles_per_s": round(cycles / seq, 3),
+        "speedup_vs_sequential": round(seq / bt, 4),
+        "tuned_config": cfg_best,
+        "tuned_forecast_ms_per_step": round(fms, 4),
+        "tuned_analysis_ms": round(ams, 4),
+        "states_equal_to_sequential": same,
+        "max_abs_state_diff_vs_sequential": maxdiff,
+        "roofline_forecast": {"kernel": "stream_collide_batch", "bound": "hbm",
+                              "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "algorithmic_bytes": int(fc_bytes),
+                              "avg_launch_us": round(fms * 1e3, 2)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,7 +268,9 @@ def main() -> int:
     ap.add_argument("--route", default="auto", choices=["auto", "ensemble", "observation"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision and differentiation forms")
+                    help="skip the precision, batching and differentiation forms")
+    ap.add_argument("--batch-cycles", type=int, default=20,
+                    help="timed cycles of the batching form")
     ap.add_argument("--grad-reps", type=int, default=20,
                     help="timed misfit gradients of the differentiation form")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -273,6 +356,10 @@ def main() -> int:
                                              storage=binding.STORAGE_F32_DEV)
         el32, d32, ms32, n32 = run_form(f32ctx)
         log(f"precision form: timed {args.steps} cycles in {el32:.3f} s")
+        log("batching form: twelve problems")
+        forms["batching"] = batching_form(args.batch_cycles, 3)
+        log(f"batching: {forms['batching']['cycles_per_s']} cycles/s "
+            f"({forms['batching']['speedup_vs_sequential']}x sequential)")
         for name, st in (("differentiation", binding.STORAGE_F32_DEV),
                          ("differentiation_f64", binding.STORAGE_F64)):
             forms[name] = differentiation_form(args.grad_reps, st)
