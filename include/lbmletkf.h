@@ -81,7 +81,11 @@ typedef enum { LBMLETKF_F64 = 0, LBMLETKF_F32_DEV = 1 } lbmletkf_storage;
  *                observations), whose eigenpairs give those of the M x M
  *                matrix: eigenvalue (M-1)/beta + lambda_i with vector
  *                Z^T u_i / sqrt(lambda_i), and (M-1)/beta on the rest;
- *   AUTO         the smaller of the two. */
+ *   AUTO         the one with the smaller estimated cost: a per-node cost
+ *                table measured on MI355X for each eigenproblem size, summed
+ *                over the nodes (the observation route sizes each node's
+ *                problem by its own local count, the ensemble route solves
+ *                M x M at every node). */
 typedef enum {
     LBMLETKF_ROUTE_AUTO = 0,
     LBMLETKF_ROUTE_ENSEMBLE = 1,

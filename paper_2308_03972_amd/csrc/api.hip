@@ -194,16 +194,46 @@ int local_counts(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o,
 
 int even_up(int n) { return (n + 1) & ~1; }
 
-// Choose the eigenproblem route and its instantiated size.
-lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, int lmax,
-                             int* route, int* n) {
+// Analysis cost per node in nanoseconds at each instantiated eigenproblem
+// size, measured on MI355X (192 x 192 grid, no localization so that every node
+// has the same size, FP64 storage; M barely matters on the observation route).
+// Only the ratios between entries are used.
+double obs_node_cost(int n) {
+    switch (n) {
+        case 8: return 7;     case 10: return 9;    case 12: return 12;   case 14: return 16;
+        case 16: return 20;   case 18: return 30;   case 20: return 40;   case 22: return 62;
+        case 24: return 75;   case 26: return 86;   case 28: return 103;  case 30: return 155;
+        case 32: return 185;  case 40: return 550;  case 48: return 840;  case 56: return 1200;
+        default: return 1700;
+    }
+}
+
+double ens_node_cost(int n) {
+    switch (n) {
+        case 8: return 16;    case 16: return 60;   case 24: return 150;
+        case 32: return 320;  case 48: return 750;  default: return 1800;
+    }
+}
+
+// Choose the eigenproblem route and its instantiated size.  AUTO sums the
+// per-node cost of each route over the nodes: the observation route sizes each
+// node's problem by that node's own local count (counts[i] points), the
+// ensemble route solves an M x M problem at every node.
+lbmletkf_status choose_route(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o,
+                             const std::vector<int>& counts, int lmax, int* route, int* n) {
     const int nz = o->nvar * lmax;
     const int nE = ens_size_for(even_up(p->members));
     const int nO = obs_size_for(even_up(nz));
     int r = o->route;
     if (r == LBMLETKF_ROUTE_AUTO) {
-        if (nO == 0) r = LBMLETKF_ROUTE_ENSEMBLE;
-        else r = (nO < nE) ? LBMLETKF_ROUTE_OBSERVATION : LBMLETKF_ROUTE_ENSEMBLE;
+        if (nO == 0) {
+            r = LBMLETKF_ROUTE_ENSEMBLE;
+        } else {
+            double cost_obs = 0.0;
+            for (int c : counts) cost_obs += obs_node_cost(obs_size_for(even_up(o->nvar * c)));
+            const double cost_ens = (double)counts.size() * ens_node_cost(nE);
+            r = (cost_obs < cost_ens) ? LBMLETKF_ROUTE_OBSERVATION : LBMLETKF_ROUTE_ENSEMBLE;
+        }
     }
     const int sz = (r == LBMLETKF_ROUTE_OBSERVATION) ? nO : nE;
     if (sz == 0)
@@ -348,7 +378,7 @@ lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
     std::vector<int> counts;
     const int lmax = local_counts(lbm, obs, &counts);
     int route = 0, n = 0;
-    if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
+    if ((st = choose_route(lbm, obs, counts, lmax, &route, &n))) return st;
     *bytes = make_layout(lbm, obs, lmax, route, gbuf_doubles(counts, obs->nvar)).total;
     return LBMLETKF_OK;
 }
@@ -358,9 +388,10 @@ lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs
     lbmletkf_status st = check_lbm(lbm);
     if (st) return st;
     if ((st = check_obs(obs, lbm))) return st;
-    const int lmax = local_counts(lbm, obs, nullptr);
+    std::vector<int> counts;
+    const int lmax = local_counts(lbm, obs, &counts);
     int r = 0, n = 0;
-    if ((st = choose_route(lbm, obs, lmax, &r, &n))) return st;
+    if ((st = choose_route(lbm, obs, counts, lmax, &r, &n))) return st;
     if (max_local_points) *max_local_points = lmax;
     if (eig_size) *eig_size = n;
     if (route) *route = r;
@@ -380,7 +411,7 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
     std::vector<int> counts;
     const int lmax = local_counts(lbm, obs, &counts);
     int route = 0, n = 0;
-    if ((st = choose_route(lbm, obs, lmax, &route, &n))) return st;
+    if ((st = choose_route(lbm, obs, counts, lmax, &route, &n))) return st;
     Layout L = make_layout(lbm, obs, lmax, route, gbuf_doubles(counts, obs->nvar));
     if (bytes < L.total) return fail(LBMLETKF_EWORKSPACE, "workspace too small");
 

@@ -104,29 +104,36 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
         }
     }
     cs[lane] = make_double2(c, s);
-    // rows: S <- P^T J^T S, from the partner's row as published
-    if (paired) {
-        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)pi * RS);
-        const double sg = first ? s : -s;
+    wave_lds_sync();
+    // S <- P^T J^T S J P and U <- U J P, one double2 of the row at a time, so
+    // that only a slice of the partner's row and of the (c, s) list is live:
+    // the row mix of entries 2k, 2k+1 (from the partner's row as published; a
+    // lane without a partner takes its own row with c = 1, s = 0, which leaves
+    // it unchanged), then the column rotation of each pair (r, r+1) whose two
+    // entries are mixed, by the pair's (c, s)
+    const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)(paired ? pi : i) * RS);
+    const double sg = first ? s : -s;
 #pragma unroll
-        for (int k = 0; k < N / 2; ++k) {
-            const double2 v = pr[k];
-            S[2 * k] = c * v.x + sg * S[2 * k];
-            S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
+    for (int k = 0; k < N / 2; ++k) {
+        const double2 v = pr[k];
+        S[2 * k] = c * v.x + sg * S[2 * k];
+        S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
+        const int r = 2 * k - P;
+        if (r >= 0) {
+            const double2 q = cs[sbase + r];
+            const double a0 = S[r], a1 = S[r + 1];
+            S[r] = q.y * a0 + q.x * a1;
+            S[r + 1] = q.x * a0 - q.y * a1;
+            const double u0 = U[r], u1 = U[r + 1];
+            U[r] = q.y * u0 + q.x * u1;
+            U[r + 1] = q.x * u0 - q.y * u1;
         }
     }
-    wave_lds_sync();
-    // columns: S <- S J P, U <- U J P, pair (r, r+1) rotated by its first lane's (c, s)
+    // pin this round's U rotations here: otherwise the compiler sinks them into
+    // the next round, next to their first use, which keeps every (c, s) of
+    // the round live (about N more doubles per lane) and costs occupancy
 #pragma unroll
-    for (int r = P; r + 1 < N; r += 2) {
-        const double2 q = cs[sbase + r];
-        const double a0 = S[r], a1 = S[r + 1];
-        S[r] = q.y * a0 + q.x * a1;
-        S[r + 1] = q.x * a0 - q.y * a1;
-        const double u0 = U[r], u1 = U[r + 1];
-        U[r] = q.y * u0 + q.x * u1;
-        U[r + 1] = q.x * u0 - q.y * u1;
-    }
+    for (int r = 0; r < N; ++r) asm volatile("" : "+v"(U[r]), "+v"(S[r]));
 }
 
 // Sweeps until every segment's off-diagonal Frobenius norm is below 1e-13
