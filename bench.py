@@ -224,9 +224,11 @@ def batching_form(cycles: int, warmup: int):
     # batched, tuned, graph replay
     states = [c.init_equilibrium(m) for c, m in zip(ctxs, mem)]
     batch = binding.Batch(ctxs, states, s)
-    cfg_best, fms, ams = batch.tune(reps=3)
+    # tune on cycled states: the Jacobi sweep count, hence the analysis cost,
+    # grows once the analyses have correlated the members
     for c in range(warmup):
         batch.run_cycle([yos[k][c] for k in range(len(cfgs))])
+    cfg_best, fms, ams = batch.tune(reps=3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for c in range(warmup, total):
@@ -330,14 +332,16 @@ def main() -> int:
     log(f"truth and {total} observation sets ready")
 
     def run_form(ctx):
-        """Warmup + timed cycles of one form; returns (elapsed s, diag, stage ms, counts)."""
+        """Warmup + timed cycles of one form; returns (elapsed s, diag, stage ms and
+        counts of the timed region, stage ms per cycle of a per-launch pass)."""
         diag = torch.zeros((total, 2 * binding.DIAG_LEN), dtype=torch.float64, device=dev)
         fe = ctx.init_equilibrium(cuda(mem_uv))
         for c in range(args.warmup):
             ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
         torch.cuda.synchronize()
-        # timed region: per-launch HIP events on the launch stream
-        ctx.set_profiling(True)
+        # timed region: HIP events on the launch stream around each cycle's
+        # forecast steps and around each analysis (level 2: one pair each)
+        ctx.set_profiling(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for c in range(args.warmup, total):
@@ -346,15 +350,23 @@ def main() -> int:
         el = time.perf_counter() - t0
         ms, n = ctx.profile_collect()
         ctx.set_profiling(False)
-        return el, diag[args.warmup:].cpu().numpy(), ms, n
+        # stage breakdown: five more cycles with an event pair around every launch
+        scratch = torch.zeros(2 * binding.DIAG_LEN, dtype=torch.float64, device=dev)
+        ctx.set_profiling(True)
+        for c in range(total - 5, total):
+            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], scratch)
+        ms1, n1 = ctx.profile_collect()
+        ctx.set_profiling(False)
+        breakdown = {binding.STAGES[k]: round(ms1[k] / 5, 4) for k in range(binding.NSTAGES)}
+        return el, diag[args.warmup:].cpu().numpy(), ms, n, breakdown
 
-    elapsed, d, stage_ms, stage_n = run_form(ectx)
+    elapsed, d, stage_ms, stage_n, breakdown = run_form(ectx)
     log(f"plain form: timed {args.steps} cycles in {elapsed:.3f} s")
     forms = {}
     if not args.no_forms:
         f32ctx = binding.Context.from_config(cfg, force=force, route=route,
                                              storage=binding.STORAGE_F32_DEV)
-        el32, d32, ms32, n32 = run_form(f32ctx)
+        el32, d32, ms32, n32, _ = run_form(f32ctx)
         log(f"precision form: timed {args.steps} cycles in {el32:.3f} s")
         log("batching form: twelve problems")
         forms["batching"] = batching_form(args.batch_cycles, 3)
@@ -434,7 +446,11 @@ def main() -> int:
         "rmse_f_mean": float(rmse_f.mean()),
         "obs_noise_rms": cfg.sigma * math.sqrt(2.0),
         "nonfinite": nonfinite,
-        "stage_ms_per_cycle": {k: round(v, 4) for k, v in per_cycle.items()},
+        "stage_ms_per_cycle": {"stream_collide": round(per_cycle["stream_collide"], 4),
+                               "analysis": round(per_cycle["analysis"], 4),
+                               "other": round(1e3 * elapsed / args.steps - per_cycle["stream_collide"]
+                                              - per_cycle["analysis"], 4)},
+        "stage_ms_per_cycle_per_launch_events": breakdown,
         "roofline": dominant,
         "roofline_other": other,
     }

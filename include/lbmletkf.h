@@ -268,7 +268,8 @@ lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
  * batch; a context must not run other calls concurrently with its batch. */
 typedef struct {
     int32_t forecast_blocks;    /* persistent blocks of the forecast launch, 1..2^20 */
-    int32_t tile_rows;          /* forecast tile = tile_rows x (256 / M) nodes, 1..64 */
+    int32_t tile_rows;          /* forecast tile = tile_rows x 256 / (M / V) nodes, 1..64; V = 2
+                                   members per thread with FP32 storage and even M, else 1 */
     int32_t bucket_granularity; /* eigenproblem sizes rounded up to multiples of 2, 4 or 8 */
     int32_t use_graph;          /* 1: capture the cycle once as a hipGraph and replay it */
 } lbmletkf_batch_config;
@@ -306,12 +307,18 @@ lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_co
 
 lbmletkf_status lbmletkf_batch_destroy(void* batch);
 
-/* Per-stage GPU timing with HIP events on the launch stream.  When enabled,
- * every launch is bracketed by an event pair; lbmletkf_profile_collect waits
- * for them and returns, per stage, the summed milliseconds and launch counts,
- * then clears the record.  Stages: 0 stream-collide (also the steps of the
- * misfit sweeps), 1 observe, 2 obs statistics, 3 analysis, 4 diagnostics,
- * 5 adjoint step, 6 misfit terms. */
+/* Per-stage GPU timing with HIP events on the launch stream.  enable = 1:
+ * every launch is bracketed by an event pair; enable = 2: one pair around the
+ * forecast steps of each lbm_ensemble_step call (its launch count = the
+ * steps) and one around each analysis, nothing else (an event pair costs
+ * the stream a few microseconds, so level 2 keeps the timing live at a small
+ * fraction of the per-launch cost; its per-launch figure includes the gaps
+ * between the back-to-back launches); 0 turns timing off.  Other values:
+ * LBMLETKF_EINVAL.  lbmletkf_profile_collect waits for the pairs and returns,
+ * per stage, the summed milliseconds and launch counts, then clears the
+ * record.  Stages: 0 stream-collide (also the steps of the misfit sweeps),
+ * 1 observe, 2 obs statistics, 3 analysis (all node groups of one call),
+ * 4 diagnostics, 5 adjoint step, 6 misfit terms. */
 #define LBMLETKF_NSTAGES 7
 lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable);
 lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts);

@@ -460,8 +460,11 @@ class Context:
         lbmletkf_misfit_backward(self, f0, cs, steps_per_obs, yo, work, g, gcs, stream)
         return g, gcs
 
-    def set_profiling(self, enable: bool) -> None:
-        _check(load().lbmletkf_set_profiling(self.handle, 1 if enable else 0))
+    def set_profiling(self, enable) -> None:
+        """False/0: off; True/1: an event pair per launch; 2: one pair per forecast
+        call (all its steps) and one per analysis."""
+        level = 2 if (not isinstance(enable, bool) and enable == 2) else (1 if enable else 0)
+        _check(load().lbmletkf_set_profiling(self.handle, level))
 
     def profile_collect(self) -> Tuple[np.ndarray, np.ndarray]:
         ms = (_c_double * NSTAGES)()

@@ -75,12 +75,14 @@ struct Ctx {
         const void* work = nullptr;
     } fwd;
     // per-stage timing
-    bool profiling = false;
+    int profiling = 0;  // 0 off, 1 every launch, 2 per call: forecast steps and analysis
     struct Rec {
         int stage;
         hipEvent_t a, b;
+        int launches;
     };
     std::vector<Rec> recs;
+    std::vector<hipEvent_t> event_pool;  // events of collected records, reused
 
     void* fbuf() const { return ws + L.fbuf; }
     int storage() const { return lbm.storage; }
@@ -104,24 +106,43 @@ struct Ctx {
     double* gbuf() const { return reinterpret_cast<double*>(ws + L.gbuf); }
 };
 
-// RAII event pair around one launch when profiling is on.
+// RAII event pair when profiling is on.  `levels`: the profiling levels at
+// which this site records (bit 1: every launch, bit 2: per call); `launches`:
+// the launches the pair spans.
+constexpr int kPerLaunch = 1 << 1, kPerCall = 1 << 2;
 struct StageTimer {
     Ctx* c;
     int stage;
     hipStream_t s;
+    int launches;
     hipEvent_t a = nullptr, b = nullptr;
-    StageTimer(Ctx* ctx, int st, hipStream_t stream) : c(ctx), stage(st), s(stream) {
-        if (!c->profiling) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    StageTimer(Ctx* ctx, int st, hipStream_t stream, int levels = kPerLaunch, int n = 1)
+        : c(ctx), stage(st), s(stream), launches(n) {
+        if (!c->profiling || !((1 << c->profiling) & levels) || n < 1) return;
+        a = take();
+        b = take();
+        if (!a || !b) {
+            if (a) c->event_pool.push_back(a);
+            if (b) c->event_pool.push_back(b);
             a = b = nullptr;
             return;
         }
         (void)hipEventRecord(a, s);
     }
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!c->event_pool.empty()) {
+            e = c->event_pool.back();
+            c->event_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
     ~StageTimer() {
         if (!a) return;
         (void)hipEventRecord(b, s);
-        c->recs.push_back({stage, a, b});
+        c->recs.push_back({stage, a, b, launches});
     }
 };
 
@@ -518,6 +539,7 @@ lbmletkf_status lbmletkf_destroy(void* ctx) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     release_streams(c);
     delete c;
     return LBMLETKF_OK;
@@ -556,6 +578,7 @@ lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* st
     hipStream_t s = as_stream(stream);
     void* a = d_f;
     void* b = c->fbuf();
+    StageTimer all(c, kStageCollide, s, kPerCall, nsteps);
     for (int k = 0; k < nsteps; ++k) {
         StageTimer t(c, kStageCollide, s);
         hipError_t e = launch_stream_collide(a, b, c->force(), c->dims, c->lbm.tau0, c->lbm.cs,
@@ -592,7 +615,7 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
         if (e != hipSuccess) return hip_fail(e, "obs_stats");
     }
     const AnalysisParams p = make_params(c, d_f);
-    StageTimer t(c, kStageAnalysis, s);
+    StageTimer t(c, kStageAnalysis, s, kPerLaunch | kPerCall);
     hipError_t e = hipSuccess;
     if (c->route == LBMLETKF_ROUTE_OBSERVATION) {
         // the largest group on the caller's stream, the others forked onto the
@@ -837,7 +860,8 @@ lbmletkf_status lbmletkf_local_histogram(void* ctx, int32_t* hist, int32_t len) 
 lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable) {
     Ctx* c = as_ctx(ctx);
     if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
-    c->profiling = enable != 0;
+    if (enable < 0 || enable > 2) return fail(LBMLETKF_EINVAL, "profiling level must be 0, 1 or 2");
+    c->profiling = enable;
     return LBMLETKF_OK;
 }
 
@@ -855,9 +879,9 @@ lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts)
         if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
         if (e != hipSuccess && st == LBMLETKF_OK) st = hip_fail(e, "profile_collect");
         ms[r.stage] += t;
-        counts[r.stage] += 1;
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+        counts[r.stage] += r.launches;
+        c->event_pool.push_back(r.a);
+        c->event_pool.push_back(r.b);
     }
     c->recs.clear();
     return st;
@@ -978,7 +1002,10 @@ lbmletkf_status batch_tasks(Batch* b, hipStream_t s) {
     for (int k = 0; k < n; ++k) {
         const Ctx* c = b->ctx[k];
         const int M = c->dims.members;
-        const int tile_nodes = b->cfg.tile_rows * (256 / M);
+        // a tile row is one block's worth of nodes: 256 threads, M / V per node
+        // (V = 2 members per thread for FP32 storage with even M)
+        const int V = (c->storage() == kStoreF32Dev && M % 2 == 0) ? 2 : 1;
+        const int tile_nodes = b->cfg.tile_rows * (256 / (M / V));
         const int plane = c->dims.nx * c->dims.ny;
         for (int v = 0; v < 3; ++v) {
             LbmTask& x = t[v * n + k];

@@ -57,12 +57,18 @@ __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double
     }
 }
 
-// Pull, collide and store one (node, member).
-template <typename T>
+// V consecutive members per thread: FP32 deviations move 4 bytes per member,
+// and one 8-byte access per population for two members keeps the wavefront's
+// requests as wide as in FP64.
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// Pull, collide and store one node for members m .. m + V - 1.
+template <typename T, int V>
 __device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restrict__ fout,
                                            const double* __restrict__ force, int nx, int ny,
                                            int members, int node, int m, double tau0,
                                            double smag, double mu) {
+    static_assert(V == 1 || (V == 2 && sizeof(T) == 4), "two members per thread: FP32 only");
     const int plane = nx * ny;
     const int y = node / nx, x = node - y * nx;
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
@@ -73,26 +79,54 @@ __device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restr
                            rm + xm, rp + xp, rp + xm, rm + xp};
     // every population is read once and written once per step: stream it
     // past the caches (nontemporal loads and stores)
-    double f[9];
+    double f[V][9];
+    if constexpr (V == 1) {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(fin + slot(src[a], a, m, members), a);
+        for (int a = 0; a < 9; ++a) f[0][a] = PopIO<T>::load_nt(fin + slot(src[a], a, m, members), a);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const float2v g = __builtin_nontemporal_load(
+                reinterpret_cast<const float2v*>(fin + slot(src[a], a, m, members)));
+            f[0][a] = w_of(a) + (double)g.x;
+            f[1][a] = w_of(a) + (double)g.y;
+        }
+    }
     double fx = 0.0, fy = 0.0;
     if (force) {
         fx = force[node];
         fy = force[plane + node];
     }
-    collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
+    for (int k = 0; k < V; ++k) collide_node(f[k], tau0, smag, fx, fy, mu);
+    if constexpr (V == 1) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[0][a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            float2v g;
+            g.x = (float)(f[0][a] - w_of(a));
+            g.y = (float)(f[1][a] - w_of(a));
+            __builtin_nontemporal_store(g, reinterpret_cast<float2v*>(fout + slot(node, a, m, members)));
+        }
+    }
 }
 
-template <typename T>
+// Members per thread of the forecast kernels: 2 for FP32 storage with an even
+// ensemble, else 1 (the single and the batched step use the same choice, so
+// they round identically).
+__host__ __device__ constexpr int members_per_thread(int elem_bytes, int members) {
+    return (elem_bytes == 4 && members % 2 == 0) ? 2 : 1;
+}
+
+template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void stream_collide_kernel(
     const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
     int ny, int members, double tau0, double smag, double mu) {
     const int node = blockIdx.x * blockDim.y + threadIdx.y;
     if (node >= nx * ny) return;
-    lbm_update<T>(fin, fout, force, nx, ny, members, node, threadIdx.x, tau0, smag, mu);
+    lbm_update<T, V>(fin, fout, force, nx, ny, members, node, threadIdx.x * V, tau0, smag, mu);
 }
 
 // Many problems in one persistent launch: blocks of 256 threads walk the
@@ -108,16 +142,23 @@ __global__ __launch_bounds__(kBlock) void stream_collide_batch_kernel(const LbmT
         while (k + 1 < ntasks && tasks[k + 1].tile0 <= t) ++k;
         const LbmTask& tk = tasks[k];
         const int M = tk.members;
-        const int npb = kBlock / M;
+        const int V = members_per_thread((int)sizeof(T), M);
+        const int tpn = M / V;  // threads per node
+        const int npb = kBlock / tpn;
         const int plane = tk.nx * tk.ny;
         const int node0 = (t - tk.tile0) * tk.tile_nodes;
-        const int m = threadIdx.x % M, nl = threadIdx.x / M;
+        const int m = (threadIdx.x % tpn) * V, nl = threadIdx.x / tpn;
         if (nl >= npb) continue;
         for (int r = nl; r < tk.tile_nodes; r += npb) {
             const int node = node0 + r;
             if (node >= plane) break;
-            lbm_update<T>(static_cast<const T*>(tk.fin), static_cast<T*>(tk.fout), tk.force, tk.nx,
-                          tk.ny, M, node, m, tk.tau0, tk.smag, tk.mu);
+            if (V == 2)
+                lbm_update<T, members_per_thread((int)sizeof(T), 2)>(
+                    static_cast<const T*>(tk.fin), static_cast<T*>(tk.fout), tk.force, tk.nx,
+                    tk.ny, M, node, m, tk.tau0, tk.smag, tk.mu);
+            else
+                lbm_update<T, 1>(static_cast<const T*>(tk.fin), static_cast<T*>(tk.fout), tk.force,
+                                 tk.nx, tk.ny, M, node, m, tk.tau0, tk.smag, tk.mu);
         }
     }
 }
@@ -216,15 +257,20 @@ int grid_for(size_t total, int block) {
 hipError_t launch_stream_collide(const void* fin, void* fout, const double* force, LbmDims d,
                                  double tau0, double cs, double mu, int storage, hipStream_t s) {
     const int plane = d.nx * d.ny;
-    const int npb = nodes_per_block(d.members);
-    const dim3 block(d.members, npb);
+    const int V = members_per_thread((int)state_elem_bytes(storage), d.members);
+    const int tpn = d.members / V;
+    const int npb = nodes_per_block(tpn);
+    const dim3 block(tpn, npb);
     const dim3 grid((plane + npb - 1) / npb);
     const double smag = 18.0 * sqrt(2.0) * cs * cs;
-    if (storage == kStoreF32Dev)
-        stream_collide_kernel<float><<<grid, block, 0, s>>>(
+    if (storage == kStoreF32Dev && V == 2)
+        stream_collide_kernel<float, 2><<<grid, block, 0, s>>>(
+            (const float*)fin, (float*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
+    else if (storage == kStoreF32Dev)
+        stream_collide_kernel<float, 1><<<grid, block, 0, s>>>(
             (const float*)fin, (float*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
     else
-        stream_collide_kernel<double><<<grid, block, 0, s>>>(
+        stream_collide_kernel<double, 1><<<grid, block, 0, s>>>(
             (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
     return hipGetLastError();
 }

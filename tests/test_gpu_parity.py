@@ -327,3 +327,33 @@ def test_analysis_is_deterministic():
         ctx, got, ref, before = _analysis_case(TINY, fe, ft, binding.ROUTE_OBSERVATION)
         outs.append(got)
     np.testing.assert_array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# per-stage timing levels (the benchmark's measurement path)
+
+def test_profiling_levels_count_launches():
+    say("profiling levels")
+    ctx = context(TINY)
+    truth_uv, mem_uv = inputs.initial_velocities(TINY)
+    f = ctx.init_equilibrium(cuda(mem_uv))
+    yo = torch.zeros(ctx.n_obs, dtype=torch.float64, device="cuda")
+    # level 1: a pair per launch
+    ctx.set_profiling(True)
+    ctx.run_cycle(f, 7, yo)
+    ms, n = ctx.profile_collect()
+    assert list(n[:4]) == [7, 1, 1, 1] and n[4] == 0
+    assert np.all(ms[:4] > 0)
+    # level 2: one pair around the seven forecast steps, one around the analysis
+    ctx.set_profiling(2)
+    ctx.run_cycle(f, 7, yo)
+    ctx.run_cycle(f, 3, yo)
+    ms2, n2 = ctx.profile_collect()
+    assert list(n2) == [10, 0, 0, 2, 0, 0, 0]
+    assert ms2[0] > 0 and ms2[3] > 0
+    ctx.set_profiling(False)
+    ctx.run_cycle(f, 2, yo)
+    _, n0 = ctx.profile_collect()
+    assert not np.any(n0)
+    st = binding.load().lbmletkf_set_profiling(ctx.handle, 3)
+    assert st == -1

@@ -51,12 +51,14 @@ def test_f32_storage_roundtrip_and_layout():
                                    atol=1e-12)
 
 
-def test_f32_stream_collide_step_matches_oracle():
-    say("f32 stream_collide one step")
+@pytest.mark.parametrize("members", [1, 4, 5, 64])
+def test_f32_stream_collide_step_matches_oracle(members):
+    """Even ensembles take two members per thread (8-byte accesses), odd ones one."""
+    say(f"f32 stream_collide one step, {members} members")
     rng = np.random.default_rng(201)
-    canon = random_state(rng, 4, 23, 37)
+    canon = random_state(rng, members, 23, 37)
     force = 1e-4 * rng.standard_normal((2, 23, 37))
-    ctx = binding.Context(37, 23, 4, 0.55, 0.15, [[0, 0]], 2, (0.1, 0.1), 2.0, 1.05,
+    ctx = binding.Context(37, 23, members, 0.55, 0.15, [[0, 0]], 2, (0.1, 0.1), 2.0, 1.05,
                           force=cuda(force), storage=F32)
     f = ctx.import_canonical(cuda(canon))
     start = host(ctx.export_canonical(f))          # the FP32-rounded input
