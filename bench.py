@@ -239,6 +239,7 @@ def batching_form(cycles: int, warmup: int):
     maxdiff = max(float((a.double() - b.double()).abs().max()) for a, b in zip(states, seq_states))
     batch.close()
     fc_bytes = 72.0 * node_members
+    rec = traffic_record("stream_collide_batch_kernel")
     gbs = fc_bytes / (fms * 1e-3) / 1e9
     return {
         "workload": ("12 problems: grids {128,192,256,384}^2 x members {16,32,64}, "
@@ -256,6 +257,7 @@ def batching_form(cycles: int, warmup: int):
         "roofline_forecast": {"kernel": "stream_collide_batch", "bound": "hbm",
                               "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "traffic": rec["bytes_per_launch"] if rec else None,
                               "algorithmic_bytes": int(fc_bytes),
                               "avg_launch_us": round(fms * 1e3, 2)},
     }
