@@ -121,7 +121,7 @@ lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
  * (F_x, F_y) or NULL for none; it is copied into the workspace.  The
  * workspace (caller-owned, >= lbmletkf_workspace_bytes) must stay valid until
  * lbmletkf_destroy.  Builds the per-node local-observation table on the GPU
- * (a4: observations with Gaspari-Cohn weight > 0) and waits for it. */
+ * (observations with Gaspari-Cohn weight > 0) and waits for it. */
 lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
                                 const double* d_force, void* d_workspace, size_t bytes,
                                 void* stream, void** ctx_out);
@@ -138,15 +138,15 @@ lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const 
 lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, void* d_f, void* stream);
 lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical, void* stream);
 
-/* a1 -- forecast (Sec. 2 LBE): advance every member nsteps >= 0 steps of
+/* Forecast (Sec. 2 LBE): advance every member nsteps >= 0 steps of
  * fused pull-stream + collide, in place on d_f (storage layout; the
  * workspace holds the ping-pong partner). */
 lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* stream);
 
-/* a2 -- observation operator y = H x (Sec. 3): d_yf[M][nvar * n_points]. */
+/* Observation operator y = H x (Sec. 3): d_yf[M][nvar * n_points]. */
 lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream);
 
-/* a3..a8 -- LETKF analysis (Sec. 3.2.1, Sec. 3.2.2), in place on d_f:
+/* LETKF analysis (Sec. 3.2.1, Sec. 3.2.2), in place on d_f:
  * ensemble statistics of d_yf against d_yo[nvar * n_points], then at every
  * node the localized ensemble-space problem, its symmetric
  * eigendecomposition, w_bar, dW = [(M-1) P~a]^(1/2) and
@@ -154,7 +154,7 @@ lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream);
 lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
                               void* stream);
 
-/* a9 -- ensemble diagnostics into d_diag[LBMLETKF_DIAG_LEN]: RMSE of the
+/* Ensemble diagnostics into d_diag[LBMLETKF_DIAG_LEN]: RMSE of the
  * ensemble-mean velocity against d_truth_uv ([2][ny][nx]; Sec. 4.3.1), spread,
  * non-finite count, min/max density.  d_truth_uv may be NULL (RMSE = 0). */
 #define LBMLETKF_DIAG_LEN 8
@@ -166,11 +166,16 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
 lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream);
 
-/* a10 -- one forecast-analysis cycle (Sec. 3 workflow (ii)-(iv)):
+/* One forecast-analysis cycle (Sec. 3 workflow (ii)-(iv)):
  * lbm_ensemble_step(nsteps) -> observe -> letkf_analyze.  d_yo: this
  * cycle's observations.  If d_diag is not NULL it receives the forecast
  * diagnostics in d_diag[0..7] and the analysis diagnostics in d_diag[8..15]
- * (d_truth_uv as in lbmletkf_diagnostics). */
+ * (d_truth_uv as in lbmletkf_diagnostics): the same quantities as
+ * lbmletkf_diagnostics, computed by the analysis kernels from each node's
+ * forecast and analysis (no extra pass over the state) and summed over the
+ * nodes in a fixed order of their own, so they agree with separate
+ * lbmletkf_diagnostics calls to rounding.  The ensemble must have >= 2
+ * members (LBMLETKF_EINVAL before any launch otherwise). */
 lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_yo,
                           const double* d_truth_uv, double* d_diag, void* stream);
 

@@ -34,7 +34,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t fbuf, force, loc_pt, loc_g, pts, ybar, dY, dvec, K, yf, partial, counters, nodes, gbuf,
-        total;
+        diag_node, diag_fold, total;
 };
 
 // Nodes of the observation route grouped by eigenproblem size.
@@ -104,6 +104,8 @@ struct Ctx {
     int* counters() const { return reinterpret_cast<int*>(ws + L.counters); }
     int* nodes() const { return reinterpret_cast<int*>(ws + L.nodes); }
     double* gbuf() const { return reinterpret_cast<double*>(ws + L.gbuf); }
+    double* diag_node() const { return reinterpret_cast<double*>(ws + L.diag_node); }
+    double* diag_fold() const { return reinterpret_cast<double*>(ws + L.diag_fold); }
 };
 
 // RAII event pair when profiling is on.  `levels`: the profiling levels at
@@ -301,6 +303,9 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
     L.counters = take(16 * sizeof(int));
     L.nodes = take(plane * sizeof(int));
     L.gbuf = take(route == 2 ? gbuf * sizeof(double) : 0);
+    // run_cycle's diagnostics: per-node records of forecast and analysis, folds
+    L.diag_node = take(2 * plane * kDiagFieldCount * sizeof(double));
+    L.diag_fold = take((size_t)2 * diag_fold_blocks((int)plane) * kDiagFieldCount * sizeof(double));
     L.total = off;
     return L;
 }
@@ -366,6 +371,8 @@ AnalysisParams make_params(const Ctx* c, void* d_f) {
     p.a = (c->dims.members - 1) / c->obs.beta;
     p.sqrt_beta = std::sqrt(c->obs.beta);
     p.eig_fail = c->counters() + 1;
+    p.truth_uv = nullptr;
+    p.diag_node = nullptr;
     return p;
 }
 
@@ -602,19 +609,23 @@ lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream) 
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "observe");
 }
 
-lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
-                              void* stream) {
-    Ctx* c = as_ctx(ctx);
-    if (!c || !d_f || !d_yf || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
-    if (c->dims.members < 2) return fail(LBMLETKF_EINVAL, "analysis needs >= 2 members");
-    hipStream_t s = as_stream(stream);
+}  // extern "C"
+
+namespace {
+
+// The analysis of letkf_analyze; with diag_node, the analysis kernels also
+// write every node's diagnostics record of the forecast and of the analysis.
+lbmletkf_status analyze_impl(Ctx* c, void* d_f, const double* d_yf, const double* d_yo,
+                             const double* d_truth_uv, double* diag_node, hipStream_t s) {
     {
         StageTimer t(c, kStageStats, s);
         hipError_t e = launch_obs_stats(d_yf, d_yo, c->nobs, c->dims.members, c->ybar(), c->dY(),
                                         c->dvec(), c->K(), s);
         if (e != hipSuccess) return hip_fail(e, "obs_stats");
     }
-    const AnalysisParams p = make_params(c, d_f);
+    AnalysisParams p = make_params(c, d_f);
+    p.truth_uv = d_truth_uv;
+    p.diag_node = diag_node;
     StageTimer t(c, kStageAnalysis, s, kPerLaunch | kPerCall);
     hipError_t e = hipSuccess;
     if (c->route == LBMLETKF_ROUTE_OBSERVATION) {
@@ -644,6 +655,18 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "analysis");
 }
 
+}  // namespace
+
+extern "C" {
+
+lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
+                              void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_yf || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (c->dims.members < 2) return fail(LBMLETKF_EINVAL, "analysis needs >= 2 members");
+    return analyze_impl(c, d_f, d_yf, d_yo, nullptr, nullptr, as_stream(stream));
+}
+
 lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
@@ -659,15 +682,19 @@ lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_
                           const double* d_truth_uv, double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
+    if (c->dims.members < 2) return fail(LBMLETKF_EINVAL, "analysis needs >= 2 members");
     lbmletkf_status st = lbm_ensemble_step(ctx, d_f, nsteps, stream);
     if (st) return st;
-    if (d_diag && (st = lbmletkf_diagnostics(ctx, d_f, d_truth_uv, d_diag, stream))) return st;
     if ((st = observe(ctx, d_f, c->yf(), stream))) return st;
-    if ((st = letkf_analyze(ctx, d_f, c->yf(), d_yo, stream))) return st;
-    if (d_diag &&
-        (st = lbmletkf_diagnostics(ctx, d_f, d_truth_uv, d_diag + LBMLETKF_DIAG_LEN, stream)))
-        return st;
-    return LBMLETKF_OK;
+    hipStream_t s = as_stream(stream);
+    if (!d_diag) return analyze_impl(c, d_f, c->yf(), d_yo, nullptr, nullptr, s);
+    // diagnostics of the forecast and of the analysis from the analysis kernels'
+    // per-node records (they hold each node's forecast and analysis anyway)
+    if ((st = analyze_impl(c, d_f, c->yf(), d_yo, d_truth_uv, c->diag_node(), s))) return st;
+    StageTimer t(c, kStageDiag, s);
+    hipError_t e = launch_diag_nodes_final(c->diag_node(), c->dims.nx * c->dims.ny, c->diag_fold(),
+                                           d_diag, d_diag + LBMLETKF_DIAG_LEN, s);
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
 }
 
 lbmletkf_status lbmletkf_adjoint_workspace_bytes(const lbmletkf_lbm_params* lbm,
@@ -944,7 +971,7 @@ struct Batch {
 Batch* as_batch(void* b) { return reinterpret_cast<Batch*>(b); }
 
 struct BatchLayout {
-    size_t params, params_tune, tasks, yo, groups, total, group_bytes;
+    size_t params, tasks, yo, groups, total, group_bytes;
 };
 
 BatchLayout batch_layout(const std::vector<Ctx*>& ctx) {
@@ -967,8 +994,8 @@ BatchLayout batch_layout(const std::vector<Ctx*>& ctx) {
         off = align_up(off + bytes);
         return at;
     };
-    L.params = take(n * sizeof(AnalysisParams));
-    L.params_tune = take(n * sizeof(AnalysisParams));
+    // [2n]: the bound states' parameters, then the partners' (one copy at create)
+    L.params = take(2 * n * sizeof(AnalysisParams));
     L.tasks = take(3 * n * sizeof(LbmTask));
     L.yo = take(nobs * sizeof(double));
     // groups: node lists, eigen waves, apply/ensemble waves, G buffers (+ alignment slack
@@ -1280,7 +1307,7 @@ lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32
     b->ws = reinterpret_cast<char*>(d_workspace);
     b->ws_bytes = bytes;
     b->d_params = reinterpret_cast<AnalysisParams*>(b->ws + L.params);
-    b->d_params_tune = reinterpret_cast<AnalysisParams*>(b->ws + L.params_tune);
+    b->d_params_tune = b->d_params + n;
     b->d_tasks[0] = reinterpret_cast<LbmTask*>(b->ws + L.tasks);
     b->d_tasks[1] = b->d_tasks[0] + n;
     b->d_tasks[2] = b->d_tasks[0] + 2 * n;

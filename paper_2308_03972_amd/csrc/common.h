@@ -54,6 +54,8 @@ struct PopIO<double> {
     __device__ static double load_nt(const double* p, int) { return __builtin_nontemporal_load(p); }
     __device__ static void store(double* p, int, double v) { *p = v; }
     __device__ static void store_nt(double* p, int, double v) { __builtin_nontemporal_store(v, p); }
+    // the value a store followed by a load gives back
+    __device__ static double round(double v, int) { return v; }
 };
 
 template <>
@@ -66,6 +68,7 @@ struct PopIO<float> {
     __device__ static void store_nt(float* p, int a, double v) {
         __builtin_nontemporal_store((float)(v - w_of(a)), p);
     }
+    __device__ static double round(double v, int a) { return w_of(a) + (double)(float)(v - w_of(a)); }
 };
 
 inline size_t state_elem_bytes(int storage) { return storage == kStoreF32Dev ? 4 : 8; }
@@ -125,7 +128,21 @@ struct AnalysisParams {
     double a;             // (M - 1) / beta
     double sqrt_beta;
     int* eig_fail;        // count of nodes whose eigensolver hit the sweep cap
+    // cycle diagnostics folded into the analysis (NULL: none): per node the five
+    // diagnostic fields (err2, spread2, non-finite, rho min, rho max) of the
+    // forecast at diag_node[node * 5] and of the analysis at
+    // diag_node[(plane + node) * 5]; truth_uv [2][ny][nx] or NULL (err2 = 0)
+    const double* truth_uv;
+    double* diag_node;
 };
+// Fields of one diagnostics record.
+constexpr int kDiagFieldCount = 5;
+// Reduce the per-node records of the forecast and the analysis (in fixed
+// order) into two diagnostics outputs; `partial` holds
+// 2 * diag_fold_blocks(plane) * kDiagFieldCount doubles.
+int diag_fold_blocks(int plane);
+hipError_t launch_diag_nodes_final(const double* diag_node, int plane, double* partial,
+                                   double* out_forecast, double* out_analysis, hipStream_t s);
 // Ensemble route (M x M eigenproblem of size n >= M), every node.
 hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s);
 int ens_size_for(int n);              // instantiated size >= n, or 0

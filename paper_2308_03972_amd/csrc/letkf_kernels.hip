@@ -167,6 +167,9 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int m
     for (int a = 0; a < 9; ++a) {
         fv[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
     }
+    if (p.diag_node)
+        node_diag_record(fv, mem, M, node, nx * ny, p.truth_uv,
+                         p.diag_node + (size_t)node * kDiagFieldCount);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         xbar[a] = wave_sum(fv[a]) / M;
@@ -233,16 +236,23 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int m
         for (int a = 0; a < 9; ++a) se[a * N + lane] = e[a] * mu;
     }
     wave_lds_sync();
+    double xa[9];  // the analysis as stored (diagnostics)
+#pragma unroll
+    for (int a = 0; a < 9; ++a) xa[a] = 0.0;
     if (mem) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < N; ++c) acc += se[a * N + c] * U[c];
-            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a,
-                            xbar[a] + dmean[a] + acc);
+            const double v = xbar[a] + dmean[a] + acc;
+            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a, v);
+            xa[a] = PopIO<T>::round(v, a);
         }
     }
+    if (p.diag_node)
+        node_diag_record(xa, mem, M, node, nx * ny, p.truth_uv,
+                         p.diag_node + ((size_t)nx * ny + node) * kDiagFieldCount);
 }
 
 template <int N, typename T>
@@ -339,6 +349,39 @@ __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
             acc[4] = fmax(acc[4], red[4][w]);
         }
         for (int k = 0; k < kDiagFields; ++k) partial[(size_t)blockIdx.x * kDiagFields + k] = acc[k];
+    }
+}
+
+// Per-node records (diagnostics folded into the analysis): block (b, s)
+// reduces records [b * kDiagBlock, (b + 1) * kDiagBlock) of state s (0
+// forecast, 1 analysis) in a fixed tree order into partial[s][b].
+__global__ __launch_bounds__(kDiagBlock) void diag_fold_kernel(const double* __restrict__ rec,
+                                                               int plane,
+                                                               double* __restrict__ partial) {
+    __shared__ double red[kDiagFields][kDiagBlock];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kDiagBlock + t;
+    const double* r = rec + ((size_t)blockIdx.y * plane + i) * kDiagFields;
+    const bool in = i < plane;
+    red[0][t] = in ? r[0] : 0.0;
+    red[1][t] = in ? r[1] : 0.0;
+    red[2][t] = in ? r[2] : 0.0;
+    red[3][t] = in ? r[3] : INFINITY;
+    red[4][t] = in ? r[4] : -INFINITY;
+    __syncthreads();
+    for (int s = kDiagBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            red[0][t] += red[0][t + s];
+            red[1][t] += red[1][t + s];
+            red[2][t] += red[2][t + s];
+            red[3][t] = fmin(red[3][t], red[3][t + s]);
+            red[4][t] = fmax(red[4][t], red[4][t + s]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double* o = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kDiagFields;
+        for (int k = 0; k < kDiagFields; ++k) o[k] = red[k][0];
     }
 }
 
@@ -515,6 +558,23 @@ hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int sto
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     diag_final_kernel<<<1, kDiagBlock, 0, s>>>(partial, need, d.nx * d.ny, out);
+    return hipGetLastError();
+}
+
+int diag_fold_blocks(int plane) { return (plane + kDiagBlock - 1) / kDiagBlock; }
+
+hipError_t launch_diag_nodes_final(const double* diag_node, int plane, double* partial,
+                                   double* out_forecast, double* out_analysis, hipStream_t s) {
+    static_assert(kDiagFields == kDiagFieldCount, "one diagnostics record layout");
+    const int nb = diag_fold_blocks(plane);
+    diag_fold_kernel<<<dim3(nb, 2), kDiagBlock, 0, s>>>(diag_node, plane, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    diag_final_kernel<<<1, kDiagBlock, 0, s>>>(partial, nb, plane, out_forecast);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    diag_final_kernel<<<1, kDiagBlock, 0, s>>>(partial + (size_t)nb * kDiagFields, nb, plane,
+                                               out_analysis);
     return hipGetLastError();
 }
 

@@ -218,6 +218,9 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
 #pragma unroll
     for (int a = 0; a < 9; ++a)
         dx[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
+    if (p.diag_node)
+        node_diag_record(dx, mem, M, node, nx * ny, p.truth_uv,
+                         p.diag_node + (size_t)node * kDiagFieldCount);
     const double* g = gin + (size_t)item * (n * n + n);
     for (int t = lane; t < n * n + n; t += kWave) Gs[t] = g[t];
     for (int j = lane; j < n; j += kWave) {
@@ -294,6 +297,9 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
         dmv[lane] = d;
     }
     wave_lds_sync();
+    double xa[9];  // the analysis as stored (diagnostics)
+#pragma unroll
+    for (int a = 0; a < 9; ++a) xa[a] = 0.0;
     if (mem) {
         // this member's l observation perturbations, loaded together
         double z[N];
@@ -317,10 +323,15 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
             if (jj % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int a = 0; a < 9; ++a)
-            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a,
-                            xbv[a] + p.sqrt_beta * dx[a] + dmv[a] + acc[a]);
+        for (int a = 0; a < 9; ++a) {
+            const double v = xbv[a] + p.sqrt_beta * dx[a] + dmv[a] + acc[a];
+            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a, v);
+            xa[a] = PopIO<T>::round(v, a);
+        }
     }
+    if (p.diag_node)
+        node_diag_record(xa, mem, M, node, nx * ny, p.truth_uv,
+                         p.diag_node + ((size_t)nx * ny + node) * kDiagFieldCount);
 }
 
 template <int N, typename T>

@@ -112,7 +112,9 @@ def test_workspace_accounts_for_state_and_tables(lib):
                               cfg.nvar, cfg.sigmas, cfg.d_cut, cfg.beta)
     gmin = cfg.n * cfg.n * (16 * 16 + 16) * 8
     gmax = cfg.n * cfg.n * (24 * 24 + 24) * 8
-    assert state + table + gmin < nbytes < state + table + gmax + 4 * 2**20
+    # run_cycle's diagnostics: five fields per node for the forecast and the analysis
+    diag = 2 * cfg.n * cfg.n * 5 * 8
+    assert state + table + gmin + diag < nbytes < state + table + gmax + diag + 4 * 2**20
     assert nbytes % 256 == 0
 
 

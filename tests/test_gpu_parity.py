@@ -66,7 +66,7 @@ def test_init_equilibrium_and_moments():
 
 
 # ---------------------------------------------------------------------------
-# a1: stream-collide
+# stream-collide
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nx,ny,m,tau0,cs,mu", [
     (32, 32, 8, 0.52, 0.1, 0.0),     # tiny config shape
@@ -113,7 +113,7 @@ def test_stream_collide_paper_scale_one_step():
 
 
 # ---------------------------------------------------------------------------
-# a2: observation operator
+# observation operator
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nvar", [2, 3])
 def test_observe(nvar):
@@ -128,7 +128,7 @@ def test_observe(nvar):
 
 
 # ---------------------------------------------------------------------------
-# a3..a8: analysis from an identical forecast
+# analysis from an identical forecast
 # ---------------------------------------------------------------------------
 def _analysis_case(cfg, fe, ft, route, nodes=None, points=None, seed=5):
     pts = inputs.observation_points(cfg) if points is None else points
@@ -164,6 +164,45 @@ def test_analysis_tiny_all_nodes(route):
     ft, fe = config_state(TINY, spin_steps=10)
     ctx, got, ref, before = _analysis_case(TINY, fe, ft, route)
     assert ctx.route == route
+    _check_analysis(got, ref, before)
+
+
+def _global_case(n, M, p, route, seed):
+    """Every node sees all p points (no localization): every node's problem has
+    the same size, 2p observations or M members."""
+    rng = np.random.default_rng(seed)
+    fe = random_state(rng, M, n, n)
+    flat = rng.choice(n * n, size=p, replace=False)
+    pts = np.stack([flat % n, flat // n], axis=1)
+    sig = (0.01, 0.01)
+    ctx = binding.Context(n, n, M, 0.55, 0.1, pts, 2, sig, math.inf, 1.05, route=route)
+    f = ctx.import_canonical(cuda(fe))
+    yf = ctx.observe(f)
+    yf_ref = oracle.observe(fe, pts, 2)
+    yo = yf_ref.mean(axis=0) + 0.01 * rng.standard_normal(2 * p)
+    ctx.analyze(f, yf, cuda(yo))
+    got = host(ctx.export_canonical(f))
+    ref = oracle.letkf_analysis(fe, yf_ref, yo, pts, sig, math.inf, 1.05)
+    return ctx, got, ref, fe
+
+
+@pytest.mark.parametrize("points", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 24, 28, 32])
+def test_analysis_every_observation_route_size(points):
+    """Each instantiated eigenproblem size of the observation route, 8 ... 64
+    (2 p local observations, M = 64), against the oracle."""
+    say(f"analysis observation route, {2 * points} local observations")
+    ctx, got, ref, before = _global_case(11, 64, points, binding.ROUTE_OBSERVATION, 400 + points)
+    sizes = (8, 10, 12, 14, 16, 18, 20, 22, 24, 26, 28, 30, 32, 40, 48, 56, 64)
+    assert ctx.eig_size == min(n for n in sizes if n >= 2 * points)
+    _check_analysis(got, ref, before)
+
+
+@pytest.mark.parametrize("members", [7, 16, 21, 32, 40, 64])
+def test_analysis_every_ensemble_route_size(members):
+    """Each instantiated size of the ensemble route, 8 ... 64 (M padded up)."""
+    say(f"analysis ensemble route, {members} members")
+    ctx, got, ref, before = _global_case(11, members, 6, binding.ROUTE_ENSEMBLE, 500 + members)
+    assert ctx.eig_size == min(n for n in (8, 16, 24, 32, 48, 64) if n >= members + members % 2)
     _check_analysis(got, ref, before)
 
 
@@ -242,7 +281,7 @@ def test_analysis_paper_scale_sampled(route):
 
 
 # ---------------------------------------------------------------------------
-# a9: diagnostics
+# diagnostics
 # ---------------------------------------------------------------------------
 def test_diagnostics_match_oracle_and_flag_nan():
     say("diagnostics")
@@ -263,7 +302,7 @@ def test_diagnostics_match_oracle_and_flag_nan():
 
 
 # ---------------------------------------------------------------------------
-# a10: the whole cycle
+# the whole cycle
 # ---------------------------------------------------------------------------
 def _gpu_osse(cfg, cycles, route=binding.ROUTE_AUTO):
     """Truth and ensemble on the GPU from the seeded inputs; returns the
@@ -357,3 +396,40 @@ def test_profiling_levels_count_launches():
     assert not np.any(n0)
     st = binding.load().lbmletkf_set_profiling(ctx.handle, 3)
     assert st == -1
+
+
+@pytest.mark.parametrize("route,storage", [(binding.ROUTE_OBSERVATION, binding.STORAGE_F64),
+                                           (binding.ROUTE_ENSEMBLE, binding.STORAGE_F64),
+                                           (binding.ROUTE_OBSERVATION, binding.STORAGE_F32_DEV)])
+def test_run_cycle_diagnostics_equal_separate_calls(route, storage):
+    """run_cycle takes the diagnostics from the analysis kernels' per-node
+    records; the same cycle as separate calls (step, diagnostics, observe,
+    analyze, diagnostics) must give the same state bit for bit and the same
+    diagnostics to rounding (density range and counts exactly)."""
+    say(f"run_cycle diagnostics route={route} storage={storage}")
+    ft, fe = config_state(TINY, spin_steps=3)
+    ctx = binding.Context.from_config(TINY, force=cuda(inputs.body_force(TINY)), route=route,
+                                      storage=storage)
+    tctx = context(TINY, members=1)
+    truth = tctx.import_canonical(cuda(ft))
+    tctx.step(truth, 6)
+    truth_uv = cuda(oracle.moments(host(tctx.export_canonical(truth)))[1:, 0])
+    pts = inputs.observation_points(TINY)
+    rng = np.random.default_rng(77)
+    yo = cuda(oracle.observe(host(tctx.export_canonical(truth)), pts)[0]
+              + TINY.sigma * rng.standard_normal(TINY.n_obs))
+    fa = ctx.import_canonical(cuda(fe))
+    fb = ctx.import_canonical(cuda(fe))
+    diag = torch.zeros(2 * binding.DIAG_LEN, dtype=torch.float64, device="cuda")
+    ctx.run_cycle(fa, 6, yo, truth_uv, diag)
+    ctx.step(fb, 6)
+    d_f = ctx.diagnostics(fb, truth_uv)
+    ctx.analyze(fb, ctx.observe(fb), yo)
+    d_a = ctx.diagnostics(fb, truth_uv)
+    assert torch.equal(fa, fb)
+    got = host(diag)
+    for k, ref in ((0, host(d_f)), (binding.DIAG_LEN, host(d_a))):
+        np.testing.assert_allclose(got[k:k + 2], ref[:2], rtol=1e-12)
+        assert got[k + 2] == ref[2] == 0
+        assert got[k + 3] == ref[3] and got[k + 4] == ref[4]
+    assert got[0] > 0 and got[binding.DIAG_LEN] > 0
