@@ -223,18 +223,18 @@ int even_up(int n) { return (n + 1) & ~1; }
 // Only the ratios between entries are used.
 double obs_node_cost(int n) {
     switch (n) {
-        case 8: return 7;     case 10: return 9;    case 12: return 12;   case 14: return 16;
-        case 16: return 20;   case 18: return 30;   case 20: return 40;   case 22: return 62;
-        case 24: return 75;   case 26: return 86;   case 28: return 103;  case 30: return 155;
-        case 32: return 185;  case 40: return 550;  case 48: return 840;  case 56: return 1200;
-        default: return 1700;
+        case 8: return 7;     case 10: return 9;    case 12: return 13;   case 14: return 17;
+        case 16: return 21;   case 18: return 30;   case 20: return 36;   case 22: return 57;
+        case 24: return 73;   case 26: return 84;   case 28: return 96;   case 30: return 107;
+        case 32: return 118;  case 40: return 480;  case 48: return 706;  case 56: return 1120;
+        default: return 2006;
     }
 }
 
 double ens_node_cost(int n) {
     switch (n) {
-        case 8: return 16;    case 16: return 60;   case 24: return 150;
-        case 32: return 320;  case 48: return 750;  default: return 1800;
+        case 8: return 16;    case 16: return 54;   case 24: return 124;
+        case 32: return 198;  case 48: return 754;  default: return 2063;
     }
 }
 
