@@ -226,8 +226,8 @@ double obs_node_cost(int n) {
         case 8: return 7;     case 10: return 9;    case 12: return 13;   case 14: return 17;
         case 16: return 21;   case 18: return 30;   case 20: return 36;   case 22: return 57;
         case 24: return 73;   case 26: return 84;   case 28: return 96;   case 30: return 107;
-        case 32: return 118;  case 40: return 480;  case 48: return 706;  case 56: return 1120;
-        default: return 2006;
+        case 32: return 118;  case 40: return 420;  case 48: return 710;  case 56: return 1130;
+        default: return 1500;
     }
 }
 
@@ -1082,8 +1082,10 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
     };
     std::vector<std::vector<int4>> host_eig;
     std::vector<std::vector<int2>> host_waves;
+    struct NodeCopy { int* dst; const int* src; size_t count; };
+    std::vector<NodeCopy> node_copies;  // issued once the layout is known to fit
     hipError_t e = hipSuccess;
-    for (int sz = 0; sz <= 64 && e == hipSuccess; ++sz) {
+    for (int sz = 0; sz <= 64; ++sz) {
         if (!obs[sz].empty()) {
             BatchGroup grp;
             grp.route = LBMLETKF_ROUTE_OBSERVATION;
@@ -1096,9 +1098,8 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
             const int segs = obs_segments(sz);
             int base = 0;
             for (const Range& r : obs[sz]) {
-                e = hipMemcpyAsync(grp.nodes + base, b->ctx[r.k]->nodes() + r.offset,
-                                   (size_t)r.count * sizeof(int), hipMemcpyDeviceToDevice, s);
-                if (e != hipSuccess) break;
+                node_copies.push_back({grp.nodes + base, b->ctx[r.k]->nodes() + r.offset,
+                                       (size_t)r.count});
                 for (int i = 0; i < r.count; i += segs) ew.push_back(make_int4(r.k, base + i, base + r.count, 0));
                 for (int i = 0; i < r.count; ++i) aw.push_back(make_int2(r.k, base + i));
                 grp.cost += (double)r.count * ((double)sz * sz * sz + 3000.0);
@@ -1132,8 +1133,11 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
             b->groups.push_back(grp);
         }
     }
-    if (e != hipSuccess) return hip_fail(e, "batch node lists");
     if (off > b->gcap) return fail(LBMLETKF_EWORKSPACE, "batch workspace too small for its groups");
+    for (const NodeCopy& nc : node_copies) {
+        e = hipMemcpyAsync(nc.dst, nc.src, nc.count * sizeof(int), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "batch node lists");
+    }
     for (size_t i = 0; i < b->groups.size() && e == hipSuccess; ++i) {
         BatchGroup& grp = b->groups[i];
         if (!host_eig[i].empty())
@@ -1289,6 +1293,7 @@ lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32
     for (int k = 0; k < n; ++k) {
         if (!ctxs[k] || !d_f[k]) return fail(LBMLETKF_EINVAL, "NULL context or state");
         Ctx* c = as_ctx(ctxs[k]);
+        if (c->dims.members < 2) return fail(LBMLETKF_EINVAL, "analysis needs >= 2 members");
         if (256 % c->dims.members != 0)
             return fail(LBMLETKF_EUNSUPPORTED, "batched members must divide 256");
         if (k > 0 && c->storage() != v[0]->storage())

@@ -59,6 +59,32 @@ struct RowStride {
     static constexpr int value = (N % 4 == 2) ? N : N + 2;
 };
 
+// Rotation (c, s) that annihilates a_pq of the 2 x 2 block [[a_pp, a_pq], [a_pq, a_qq]]
+// (c = s = 1, 0 for a_pq = 0).  t = sgn(tau) / (|tau| + sqrt(1 + tau^2)),
+// tau = (a_qq - a_pp) / (2 a_pq), the smaller root of t^2 + 2 tau t - 1 = 0, is
+// evaluated in FP32 on operands scaled so that |a_pq| is near [1, 2): any t gives
+// an exactly orthogonal rotation through c and s below (FP64), and an
+// FP32-accurate t still removes all but ~1e-7 of a_pq, which the next sweeps
+// finish.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double* cp,
+                                                double* sp) {
+    double c = 1.0, s = 0.0;
+    if (apq != 0.0) {
+        const double d = aqq - app;
+        const double sc = ldexp(1.0, -max(ilogb(apq), -1000));
+        const float af = (float)(apq * sc);
+        const float at = fabsf((float)(d * sc)) * 0.5f * __builtin_amdgcn_rcpf(fabsf(af));
+        float tf = at > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(at)
+                              : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(1.0f + at * at));
+        if ((d < 0.0) != (apq < 0.0)) tf = -tf;
+        const double t = (double)tf;
+        c = rsqrt(1.0 + t * t);
+        s = t * c;
+    }
+    *cp = c;
+    *sp = s;
+}
+
 template <int N, int SEGS, int P>
 __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], double* rows,
                                              double2* cs, int lane) {
@@ -81,28 +107,9 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
     const bool paired = active && pi >= 0 && pi < N;
     const int p = first ? i : pi;
     double c = 1.0, s = 0.0;
-    if (paired) {
-        const double app = segrows[(size_t)p * RS + p];
-        const double aqq = segrows[(size_t)(p + 1) * RS + p + 1];
-        const double apq = segrows[(size_t)p * RS + p + 1];
-        if (apq != 0.0) {
-            // t = sgn(tau) / (|tau| + sqrt(1 + tau^2)), tau = (aqq - app) / (2 apq),
-            // the smaller root of t^2 + 2 tau t - 1 = 0, evaluated in FP32 on
-            // operands scaled so that |apq| is near [1, 2): any t gives an exactly
-            // orthogonal rotation through c and s below (FP64), and an FP32-accurate
-            // t still removes all but ~1e-7 of a_pq, which the next sweeps finish
-            const double d = aqq - app;
-            const double sc = ldexp(1.0, -max(ilogb(apq), -1000));
-            const float af = (float)(apq * sc);
-            const float at = fabsf((float)(d * sc)) * 0.5f * __builtin_amdgcn_rcpf(fabsf(af));
-            float tf = at > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(at)
-                                  : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(1.0f + at * at));
-            if ((d < 0.0) != (apq < 0.0)) tf = -tf;
-            const double t = (double)tf;
-            c = rsqrt(1.0 + t * t);
-            s = t * c;
-        }
-    }
+    if (paired)
+        jacobi_rotation(segrows[(size_t)p * RS + p], segrows[(size_t)(p + 1) * RS + p + 1],
+                        segrows[(size_t)p * RS + p + 1], &c, &s);
     cs[lane] = make_double2(c, s);
     wave_lds_sync();
     // S <- P^T J^T S J P and U <- U J P, one double2 of the row at a time, so

@@ -153,30 +153,296 @@ __device__ __forceinline__ void eig_body(const AnalysisParams p, const int* node
     }
 }
 
+// ---------------------------------------------------------------------------
+// eigen part for N > 32: one node per block of two wavefronts, every row split
+// between them -- thread (h, i) holds columns [h H, (h + 1) H) of row i of S and
+// of U (H = N / 2), N doubles per lane instead of 2 N, so two blocks fit per SIMD
+// pair instead of one wavefront.  Same rounds as the one-wavefront solver: the
+// half rows are published to LDS, half 0 derives each pair's (c, s) from the
+// published 2 x 2 blocks, every thread mixes its half row with the partner's
+// published half row and rotates the column pairs inside its half; the one
+// column pair that straddles the halves (H - 1, H), paired when P = 1, is
+// finished after trading its two entries of S and U through LDS.
+// ---------------------------------------------------------------------------
+template <int N>
+struct SplitLayout {
+    static_assert(N > 32 && N <= 64 && N % 4 == 0, "split rows need 32 < N <= 64, N / 2 even");
+    static constexpr int H = N / 2;
+    static constexpr int RS = RowStride<N>::value;
+    static constexpr int kThreads = 2 * kWave;
+    static constexpr int kRows = 2 * N * RS;       // published S, two buffers by round parity;
+                                                   // afterwards U and the G partial sums
+    static constexpr int kCs = 2 * 2 * N;          // (c, s) per row, one list per wavefront
+    static constexpr int kRed = 2 * kThreads;      // convergence partial sums
+    static constexpr int kBx = 4 * N;              // straddling column of S and U, per half
+    static constexpr int kVec = 3 * N;             // eigenvalues, psi t, phi
+    static constexpr int kObs = 2 * N + (N + 1) / 2;  // sw, dt, q
+    static constexpr int total = kRows + kCs + kRed + kBx + kVec + kObs;
+};
+
+// One round: publish the half rows into buffer `rows` (the two buffers
+// alternate, so the previous round's readers need no barrier), then every
+// thread derives its own pair's (c, s) from the published 2 x 2 block (both
+// halves of a row get identical values) and shares it within its wavefront,
+// whose column range needs only its own rows' rotations.
+template <int N, int P>
+__device__ __forceinline__ void split_round(double (&S)[N / 2], double (&U)[N / 2], double* rows,
+                                            double2* csw, double* bx, int i, int hh, bool active) {
+    constexpr int H = N / 2;
+    constexpr int RS = RowStride<N>::value;
+    const int c0 = hh * H;
+    if (active) {
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)i * RS + c0);
+#pragma unroll
+        for (int k = 0; k < H / 2; ++k) my[k] = make_double2(S[2 * k], S[2 * k + 1]);
+    }
+    __syncthreads();
+    const bool first = ((i - P) & 1) == 0;
+    const int pi = first ? i + 1 : i - 1;
+    const bool paired = active && pi >= 0 && pi < N;
+    double c = 1.0, s = 0.0;
+    if (paired) {
+        const int p = first ? i : pi;
+        jacobi_rotation(rows[(size_t)p * RS + p], rows[(size_t)(p + 1) * RS + p + 1],
+                        rows[(size_t)p * RS + p + 1], &c, &s);
+    }
+    if (active) csw[i] = make_double2(c, s);
+    wave_lds_sync();
+    const double sg = first ? s : -s;
+    // row mix from the partner's published half row (own row, c = 1, s = 0 for
+    // a row without a partner), then the column pairs inside this half
+    const int src = paired ? pi : (active ? i : 0);
+    const double2* pr = reinterpret_cast<const double2*>(rows + (size_t)src * RS + c0);
+#pragma unroll
+    for (int k = 0; k < H / 2; ++k) {
+        const double2 v = pr[k];
+        S[2 * k] = c * v.x + sg * S[2 * k];
+        S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
+        const int r = 2 * k - P;
+        if (r >= 0) {
+            const double2 q = csw[c0 + r];
+            const double a0 = S[r], a1 = S[r + 1];
+            S[r] = q.y * a0 + q.x * a1;
+            S[r + 1] = q.x * a0 - q.y * a1;
+            const double u0 = U[r], u1 = U[r + 1];
+            U[r] = q.y * u0 + q.x * u1;
+            U[r + 1] = q.x * u0 - q.y * u1;
+        }
+    }
+    if (P == 1) {
+        // the pair (H - 1, H): half 0 holds entry H - 1 (its last), half 1 entry H (its first)
+        if (active) {
+            bx[(size_t)(2 * hh) * N + i] = hh == 0 ? S[H - 1] : S[0];
+            bx[(size_t)(2 * hh + 1) * N + i] = hh == 0 ? U[H - 1] : U[0];
+        }
+        __syncthreads();
+        if (active) {
+            const double2 q = csw[H - 1];
+            const double so = bx[(size_t)(2 * (1 - hh)) * N + i];
+            const double uo = bx[(size_t)(2 * (1 - hh) + 1) * N + i];
+            if (hh == 0) {
+                S[H - 1] = q.y * S[H - 1] + q.x * so;
+                U[H - 1] = q.y * U[H - 1] + q.x * uo;
+            } else {
+                S[0] = q.x * so - q.y * S[0];
+                U[0] = q.x * uo - q.y * U[0];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < H; ++r) asm volatile("" : "+v"(U[r]), "+v"(S[r]));
+}
+
+// One block of two wavefronts: node nodes[item] (item < end) of one problem.
+template <int N>
+__device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int* nodes, int item,
+                                               int end, double* gout, int max_sweeps) {
+    using L = SplitLayout<N>;
+    constexpr int H = L::H;
+    constexpr int RS = L::RS;
+    extern __shared__ double lds[];
+    double* rows = lds;                                   // [2][N][RS]
+    double* xg = rows + N * RS;                           // second buffer, after the sweeps
+    double2* cs = reinterpret_cast<double2*>(rows + L::kRows);  // [2 halves][N]
+    double* red = rows + L::kRows + L::kCs;               // [2 * 128]
+    double* bx = red + L::kRed;                           // [2 halves][S, U][N]
+    double* lam = bx + L::kBx;                            // [N]
+    double* pt = lam + N;                                 // [N]
+    double* phv = pt + N;                                 // [N]
+    double* sw = phv + N;                                 // [N]
+    double* dt = sw + N;                                  // [N]
+    int* qx = reinterpret_cast<int*>(dt + N);             // [N]
+
+    const int t = threadIdx.x;
+    const int hh = t / kWave;
+    const int i = t - hh * kWave;
+    const bool active = i < N;
+    const int c0 = hh * H;
+    const bool valid = item < end;
+    const int node = valid ? nodes[item] : 0;
+
+    if (hh == 0 && active) {
+        int q = 0;
+        double w = 0.0, d = 0.0;
+        if (valid) local_obs(p, node, i, &q, &w, &d);
+        qx[i] = q;
+        sw[i] = w;
+        dt[i] = d;
+    }
+    __syncthreads();
+    // this thread's half of row i of S = diag(sw) K diag(sw), and of U = I
+    double S[H], U[H];
+    {
+        const double wi = active ? sw[i] : 0.0;
+        const double* Krow = p.K + (size_t)(active ? qx[i] : 0) * p.nobs;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const double wk = sw[c0 + k];
+            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * Krow[qx[c0 + k]] : 0.0;
+            U[k] = (active && c0 + k == i) ? 1.0 : 0.0;
+        }
+    }
+    // sweeps until the off-diagonal Frobenius norm is below 1e-13 of the
+    // diagonal's; every thread sums the same partials in the same order
+    int sweeps = 0;
+    for (;; ++sweeps) {
+        double off = 0.0, dg = 0.0;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const double v2 = S[k] * S[k];
+            if (c0 + k == i) dg += v2;
+            else off += v2;
+        }
+        __syncthreads();
+        red[2 * t] = active ? off : 0.0;
+        red[2 * t + 1] = active ? dg : 0.0;
+        __syncthreads();
+        double so = 0.0, sd = 0.0;
+        for (int k = 0; k < L::kThreads; ++k) {
+            so += red[2 * k];
+            sd += red[2 * k + 1];
+        }
+        if (so <= 1e-26 * sd) break;
+        if (sweeps >= max_sweeps) {
+            sweeps = max_sweeps + 1;
+            break;
+        }
+        double2* mycs = cs + hh * N;
+#pragma unroll 1
+        for (int rr = 0; rr < N / 2; ++rr) {
+            split_round<N, 0>(S, U, rows, mycs, bx, i, hh, active);
+            split_round<N, 1>(S, U, rows + N * RS, mycs, bx, i, hh, active);
+        }
+    }
+    if (sweeps > max_sweeps && t == 0) atomicAdd(p.eig_fail, 1);
+
+    // eigenvalues (the diagonal entry of row i sits in half i / H), U to LDS
+    __syncthreads();
+    if (active && i / H == hh) lam[i] = extract_lane_entry<H>(S, i - c0);
+    if (active) {
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)i * RS + c0);
+#pragma unroll
+        for (int k = 0; k < H / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
+    }
+    __syncthreads();
+    // phi_c, and psi_c t_c with t = U^T d~ (thread (0, c) for column c)
+    if (hh == 0 && active) {
+        const double lm = lam[i];
+        const double sq = sqrt(1.0 + lm / p.a);
+        const double psi = 1.0 / (p.a + lm);
+        phv[i] = -p.sqrt_beta / (p.a * sq * (1.0 + sq));
+        double tt = 0.0;
+        for (int k = 0; k < N; ++k) tt += rows[(size_t)k * RS + i] * dt[k];
+        pt[i] = psi * tt;
+    }
+    __syncthreads();
+    // G_ij = sum_c U_ic phi_c U_jc: each half sums its own columns c; a thread
+    // hands the partial sums for the other half's outputs j over through LDS
+#pragma unroll
+    for (int k = 0; k < H; ++k) U[k] *= phv[c0 + k];
+    const int oc0 = (1 - hh) * H;
+    if (active) {
+#pragma unroll 1
+        for (int j = oc0; j < oc0 + H; ++j) {
+            const double2* rj = reinterpret_cast<const double2*>(rows + (size_t)j * RS + c0);
+            double g = 0.0;
+#pragma unroll
+            for (int k = 0; k < H / 2; ++k) {
+                const double2 r = rj[k];
+                g += U[2 * k] * r.x + U[2 * k + 1] * r.y;
+            }
+            xg[(size_t)i * RS + j] = g;
+        }
+    }
+    __syncthreads();
+    if (active && valid) {
+        double* out = gout + (size_t)item * (N * N + N);
+#pragma unroll 1
+        for (int j = c0; j < c0 + H; ++j) {
+            const double2* rj = reinterpret_cast<const double2*>(rows + (size_t)j * RS + c0);
+            double g = 0.0;
+#pragma unroll
+            for (int k = 0; k < H / 2; ++k) {
+                const double2 r = rj[k];
+                g += U[2 * k] * r.x + U[2 * k + 1] * r.y;
+            }
+            out[(size_t)j * N + i] = g + xg[(size_t)i * RS + j];
+        }
+        if (hh == 0) {
+            double hs = 0.0;
+            for (int c = 0; c < N; ++c) hs += rows[(size_t)i * RS + c] * pt[c];
+            out[(size_t)N * N + i] = hs;
+        }
+    }
+}
+
 // Up to N = 18 the eigensolver fits in 168 VGPRs (three wavefronts per SIMD)
 // without spilling; larger N keep the compiler's choice.
 template <int N>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
-void analysis_eig_kernel(AnalysisParams p, const int* nodes,
-                                                          int count, double* gout,
-                                                          int max_sweeps) {
-    eig_body<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x) * EigLayout<N>::SEGS, count, gout,
-                max_sweeps);
+constexpr bool kSplitRows = N > 32;
+
+template <int N>
+constexpr int eig_threads() { return kSplitRows<N> ? 2 * kWave : kWave; }
+
+template <int N>
+constexpr int eig_lds_doubles() {
+    if constexpr (kSplitRows<N>) return SplitLayout<N>::total;
+    else return EigLayout<N>::total;
+}
+
+template <int N>
+__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
+void analysis_eig_kernel(AnalysisParams p, const int* nodes, int count, double* gout,
+                         int max_sweeps) {
+    if constexpr (kSplitRows<N>)
+        eig_body_split<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x), count, gout, max_sweeps);
+    else
+        eig_body<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x) * EigLayout<N>::SEGS, count, gout,
+                    max_sweeps);
 }
 
 // Batched form: wavefront w takes waves[w] = (problem, first item, end of the
 // problem's items); the items of all problems share one node list and one G buffer.
 template <int N>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
-void analysis_eig_batch_kernel(const AnalysisParams* P,
-                                                                const int4* waves, int nwaves,
-                                                                const int* nodes, double* gout,
-                                                                int max_sweeps) {
+__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
+void analysis_eig_batch_kernel(const AnalysisParams* P, const int4* waves, int nwaves,
+                               const int* nodes, double* gout, int max_sweeps) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     if (w >= nwaves) return;
     const int4 d = waves[w];
     const AnalysisParams p = P[d.x];
-    eig_body<N>(p, nodes, d.y, d.z, gout, max_sweeps);
+    if constexpr (kSplitRows<N>) eig_body_split<N>(p, nodes, d.y, d.z, gout, max_sweeps);
+    else eig_body<N>(p, nodes, d.y, d.z, gout, max_sweeps);
+}
+
+// Dynamic LDS beyond 64 KiB needs the kernel's permission (set once per kernel).
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes, bool* done) {
+    if (bytes <= 65536 || *done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) *done = true;
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,12 +625,15 @@ __global__ __launch_bounds__(64) void analysis_apply_batch_kernel(const Analysis
 template <int N>
 hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double* gbuf,
                     hipStream_t s) {
-    using L = EigLayout<N>;
     if (count == 0) return hipSuccess;
-    const size_t eig_bytes = (size_t)L::total * sizeof(double);
-    const int eig_blocks = (count + L::SEGS - 1) / L::SEGS;
-    analysis_eig_kernel<N><<<eig_blocks, 64, eig_bytes, s>>>(p, nodes, count, gbuf, 30);
-    hipError_t e = hipGetLastError();
+    const size_t eig_bytes = (size_t)eig_lds_doubles<N>() * sizeof(double);
+    const int segs = kSplitRows<N> ? 1 : EigLayout<N>::SEGS;
+    const int eig_blocks = (count + segs - 1) / segs;
+    static bool lds_ok = false;
+    hipError_t e = allow_lds(analysis_eig_kernel<N>, eig_bytes, &lds_ok);
+    if (e != hipSuccess) return e;
+    analysis_eig_kernel<N><<<eig_blocks, eig_threads<N>(), eig_bytes, s>>>(p, nodes, count, gbuf, 30);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
     if (p.storage == kStoreF32Dev)
@@ -378,11 +647,14 @@ template <int N>
 hipError_t launch_batch_n(const AnalysisParams* d_params, const int4* d_eig_waves, int n_eig,
                           const int2* d_apply_waves, int n_apply, const int* d_nodes,
                           double* gbuf, int storage, hipStream_t s) {
-    using L = EigLayout<N>;
     if (n_eig == 0) return hipSuccess;
-    analysis_eig_batch_kernel<N><<<n_eig, 64, (size_t)L::total * sizeof(double), s>>>(
+    const size_t eig_bytes = (size_t)eig_lds_doubles<N>() * sizeof(double);
+    static bool lds_ok = false;
+    hipError_t e = allow_lds(analysis_eig_batch_kernel<N>, eig_bytes, &lds_ok);
+    if (e != hipSuccess) return e;
+    analysis_eig_batch_kernel<N><<<n_eig, eig_threads<N>(), eig_bytes, s>>>(
         d_params, d_eig_waves, n_eig, d_nodes, gbuf, 30);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
     if (storage == kStoreF32Dev)
@@ -412,8 +684,8 @@ int obs_size_for(int n) {
 
 int obs_lds_bytes(int n) {
     switch (n) {
-#define X(v) case v: return (EigLayout<v>::total > apply_lds_doubles(v) ? EigLayout<v>::total \
-                                                                      : apply_lds_doubles(v)) * \
+#define X(v) case v: return (eig_lds_doubles<v>() > apply_lds_doubles(v) ? eig_lds_doubles<v>() \
+                                                                        : apply_lds_doubles(v)) * \
                             (int)sizeof(double);
         LBMLETKF_OBS_SIZES(X)
 #undef X
