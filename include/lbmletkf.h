@@ -253,7 +253,7 @@ lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
 /* ---- batching form: many independent problems per cycle -----------------
  *
  * A batch binds n contexts (problems of any grid, ensemble size and observing
- * network; members must divide 256 and every context must have the same
+ * network; members >= 2 must divide 256 and every context must have the same
  * storage) to their state buffers d_f[k] and advances all of them one cycle
  * (Sec. 3 workflow (ii)-(iv), as run_cycle without diagnostics) per call:
  *   - the forecast of all problems is one persistent launch per step over the
@@ -272,7 +272,8 @@ lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
  * buffers.  The contexts, state buffers and both workspaces must outlive the
  * batch; a context must not run other calls concurrently with its batch. */
 typedef struct {
-    int32_t forecast_blocks;    /* persistent blocks of the forecast launch, 1..2^20 */
+    int32_t forecast_blocks;    /* blocks of the forecast launch, 1..2^20 walking the tile
+                                   list with a fixed stride, or 0: one block per tile */
     int32_t tile_rows;          /* forecast tile = tile_rows x 256 / (M / V) nodes, 1..64; V = 2
                                    members per thread with FP32 storage and even M, else 1 */
     int32_t bucket_granularity; /* eigenproblem sizes rounded up to multiples of 2, 4 or 8 */
@@ -283,7 +284,7 @@ lbmletkf_status lbmletkf_batch_workspace_bytes(void* const* ctxs, int32_t n, siz
 
 /* Create a batch of n contexts with states d_f[k] (device, storage layout) and
  * nsteps forecast steps per cycle.  ctxs and d_f are host arrays of n pointers.
- * cfg may be NULL: {1024 blocks, 1 tile row, granularity 2, graph}.  Waits for
+ * cfg may be NULL: {one block per tile, 4 tile rows, granularity 2, graph}.  Waits for
  * its setup copies and, with use_graph, captures the cycle. */
 lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32_t n,
                                       int32_t nsteps, const lbmletkf_batch_config* cfg,
@@ -301,7 +302,7 @@ lbmletkf_status lbmletkf_batch_get_config(void* batch, lbmletkf_batch_config* cf
 lbmletkf_status lbmletkf_batch_set_config(void* batch, const lbmletkf_batch_config* cfg,
                                           void* stream);
 
-/* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048}) x
+/* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048, 0}) x
  * (tile_rows in {1, 2, 4, 8}) forecast step and every bucket granularity
  * {2, 4, 8} of the analysis (reps timed runs each, HIP events), then applies
  * the fastest with use_graph = 1.  Runs on the contexts' ping-pong partner

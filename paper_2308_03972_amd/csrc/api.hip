@@ -1210,13 +1210,19 @@ hipError_t batch_observe(Batch* b, bool partners, hipStream_t s) {
     return e;
 }
 
+// Blocks of the batched forecast launch: the configured persistent count, or
+// one block per tile (forecast_blocks = 0).
+int forecast_grid(const Batch* b) {
+    return b->cfg.forecast_blocks > 0 ? b->cfg.forecast_blocks : std::max(b->ntiles, 1);
+}
+
 // One whole cycle of every problem on stream s.
 hipError_t batch_issue_cycle(Batch* b, hipStream_t s) {
     hipError_t e = hipSuccess;
     const int n = (int)b->ctx.size();
     for (int step = 0; step < b->nsteps && e == hipSuccess; ++step)
         e = launch_stream_collide_batch(b->d_tasks[step & 1], n, b->ntiles,
-                                        b->cfg.forecast_blocks, b->storage, s);
+                                        forecast_grid(b), b->storage, s);
     if (b->nsteps & 1)
         for (int k = 0; k < n && e == hipSuccess; ++k)
             e = hipMemcpyAsync(b->f[k], b->ctx[k]->fbuf(), b->ctx[k]->state_bytes(),
@@ -1242,8 +1248,8 @@ lbmletkf_status batch_capture(Batch* b) {
 }
 
 lbmletkf_status batch_check_config(const lbmletkf_batch_config* cfg) {
-    if (cfg->forecast_blocks < 1 || cfg->forecast_blocks > (1 << 20))
-        return fail(LBMLETKF_EINVAL, "forecast_blocks must be in 1..2^20");
+    if (cfg->forecast_blocks < 0 || cfg->forecast_blocks > (1 << 20))
+        return fail(LBMLETKF_EINVAL, "forecast_blocks must be in 0..2^20");
     if (cfg->tile_rows < 1 || cfg->tile_rows > 64)
         return fail(LBMLETKF_EINVAL, "tile_rows must be in 1..64");
     if (cfg->bucket_granularity != 2 && cfg->bucket_granularity != 4 &&
@@ -1285,7 +1291,7 @@ lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32
     if (nsteps < 1) return fail(LBMLETKF_EINVAL, "nsteps must be >= 1");
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
         return fail(LBMLETKF_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-    lbmletkf_batch_config c0{256 * 4, 1, 2, 1};
+    lbmletkf_batch_config c0{0, 4, 2, 1};
     const lbmletkf_batch_config* use = cfg ? cfg : &c0;
     lbmletkf_status st = batch_check_config(use);
     if (st) return st;
@@ -1414,9 +1420,9 @@ lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_co
     lbmletkf_batch_config best_cfg = cur;
     double best_f = 1e30, best_a = 1e30;
     lbmletkf_status st = LBMLETKF_OK;
-    // forecast: persistent blocks x tile rows, stepping the bound states into their
-    // partners (the bound states are not modified)
-    const int blocks[] = {256, 512, 1024, 2048};
+    // forecast: persistent blocks (0: one block per tile) x tile rows, stepping the
+    // bound states into their partners (the bound states are not modified)
+    const int blocks[] = {256, 512, 1024, 2048, 0};
     const int rows[] = {1, 2, 4, 8};
     for (int bl : blocks) {
         for (int tr : rows) {
@@ -1426,9 +1432,10 @@ lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_co
             b->cfg = cur;
             if ((st = batch_tasks(b, s))) break;
             double ms = 0.0;
+            const int grid = forecast_grid(b);
             e = timed([&]() {
                 return launch_stream_collide_batch(b->d_tasks[2], (int)b->ctx.size(), b->ntiles,
-                                                   bl, b->storage, s);
+                                                   grid, b->storage, s);
             }, &ms);
             if (e == hipSuccess && ms < best_f) {
                 best_f = ms;

@@ -142,6 +142,19 @@ def test_batch_tuning_and_coarse_buckets():
         assert np.max(np.abs(c - s)) <= 1e-12 * scale
 
 
+def test_batch_one_block_per_tile():
+    """forecast_blocks = 0 launches one block per tile instead of a fixed-stride
+    persistent grid; the states must still equal each problem's run_cycle."""
+    say("batch one block per tile")
+    probs = _setup(_mixed_configs(), F64, cycles=2)
+    single = _single_runs(probs, 2)
+    for rows in (1, 3):
+        batched = _batch_runs(probs, 2, config=dict(forecast_blocks=0, tile_rows=rows,
+                                                    bucket_granularity=2, use_graph=1))
+        for s_, b_ in zip(single, batched):
+            assert np.array_equal(s_, b_)
+
+
 def test_batch_against_oracle():
     """Two problems (ensemble and observation route) over two cycles against the
     oracle's own forecast-analysis cycles."""
@@ -192,4 +205,10 @@ def test_batch_argument_errors():
     c4, _, _, m4 = _problem(base, F64)
     with pytest.raises(binding.LbmLetkfError) as e:      # one state bound twice
         binding.Batch([c1, c4], [f1, f1], 10)
+    assert e.value.status == -1
+    c5, _, _, m5 = _problem(base, F64)
+    c6 = binding.Context.from_config(base, members=1, storage=F64)
+    f6 = c6.init_equilibrium(m5[:1].contiguous())
+    with pytest.raises(binding.LbmLetkfError) as e:      # one member: no analysis
+        binding.Batch([c5, c6], [c5.init_equilibrium(m5), f6], 10)
     assert e.value.status == -1
