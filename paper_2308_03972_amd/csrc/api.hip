@@ -233,8 +233,8 @@ double obs_node_cost(int n) {
 
 double ens_node_cost(int n) {
     switch (n) {
-        case 8: return 16;    case 16: return 54;   case 24: return 124;
-        case 32: return 198;  case 48: return 754;  default: return 2063;
+        case 8: return 3.4;   case 16: return 16.4; case 24: return 121;
+        case 32: return 145;  case 48: return 747;  default: return 2052;
     }
 }
 
@@ -1122,7 +1122,7 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
             for (int k : ens[sz]) {
                 const Ctx* c = b->ctx[k];
                 const int plane = c->dims.nx * c->dims.ny;
-                for (int i = 0; i < plane; ++i) w.push_back(make_int2(k, i));
+                for (int i = 0; i < plane; i += ens_segments(sz)) w.push_back(make_int2(k, i));
                 grp.nz_max = std::max(grp.nz_max, c->obs.nvar * c->lmax);
                 grp.cost += (double)plane * 4.0 * sz * sz * sz;
             }

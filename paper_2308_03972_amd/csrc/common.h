@@ -147,7 +147,9 @@ hipError_t launch_diag_nodes_final(const double* diag_node, int plane, double* p
 hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s);
 int ens_size_for(int n);              // instantiated size >= n, or 0
 int ens_lds_bytes(int n, int nz);
-// Batched ensemble route: wavefront w handles waves[w] = (problem, node); nz_max
+int ens_segments(int n);              // nodes per wavefront of the ensemble route
+// Batched ensemble route: wavefront w handles waves[w] = (problem, first node of
+// its ens_segments(n) consecutive nodes of that problem); nz_max
 // is the largest nvar * lmax among the problems.
 hipError_t launch_analysis_ens_batch(const AnalysisParams* d_params, const int2* d_waves,
                                      int nwaves, int n, int nz_max, int storage, hipStream_t s);

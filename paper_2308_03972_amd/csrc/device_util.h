@@ -180,12 +180,14 @@ __device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2*
     }
 }
 
-// One node's cycle-diagnostics record from the wavefront that holds the node
-// (lane = member, lanes >= M hold nothing): the squared error of the
+// One node's cycle-diagnostics record from the group of G lanes (the whole
+// wavefront by default) that holds the node (lane = member, lanes >= M hold
+// nothing): the squared error of the
 // ensemble-mean velocity against the truth (0 without truth), the spread
 // sum_m |u_m - u_bar|^2 / (M - 1), the number of members with a non-finite
 // density or velocity, and the density range; lane 0 writes the five fields
 // to out[0..4].  The same quantities, per node, as diag_partial_kernel.
+template <int G = kWave>
 __device__ __forceinline__ void node_diag_record(const double (&f)[9], bool mem, int M, int node,
                                                  int plane, const double* truth_uv, double* out) {
     double u = 0.0, v = 0.0, rho = 1.0, bad = 0.0, rmin = INFINITY, rmax = -INFINITY;
@@ -204,7 +206,12 @@ __device__ __forceinline__ void node_diag_record(const double (&f)[9], bool mem,
         rmin = rho;
         rmax = rho;
     }
-    const double ub = wave_sum(u) / M, vb = wave_sum(v) / M;
+    auto gsum = [](double x) {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+        return x;
+    };
+    const double ub = gsum(u) / M, vb = gsum(v) / M;
     double err2 = 0.0, spr2 = 0.0;
     if (truth_uv) {
         const double du = ub - truth_uv[node], dv = vb - truth_uv[plane + node];
@@ -212,15 +219,15 @@ __device__ __forceinline__ void node_diag_record(const double (&f)[9], bool mem,
     }
     if (M > 1) {
         const double du = mem ? u - ub : 0.0, dv = mem ? v - vb : 0.0;
-        spr2 = wave_sum(du * du + dv * dv) / (M - 1);
+        spr2 = gsum(du * du + dv * dv) / (M - 1);
     }
-    bad = wave_sum(bad);
+    bad = gsum(bad);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = G / 2; off > 0; off >>= 1) {
         rmin = fmin(rmin, __shfl_xor(rmin, off, kWave));
         rmax = fmax(rmax, __shfl_xor(rmax, off, kWave));
     }
-    if (threadIdx.x % kWave == 0) {
+    if (threadIdx.x % G == 0) {
         out[0] = err2;
         out[1] = spr2;
         out[2] = bad;

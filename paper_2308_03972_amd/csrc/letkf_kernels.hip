@@ -133,53 +133,77 @@ __global__ void local_table_kernel(const int* __restrict__ pts, int npts, double
 // ensemble route: one node per wavefront, eigenproblem (M-1)/beta I + Z^T Z
 // (lane = member; sizes above M are padded with isolated (M-1)/beta rows)
 // ---------------------------------------------------------------------------
+// Nodes per wavefront of the ensemble route: N in {8, 16, 32} packs 64 / N
+// nodes (a segment of N lanes each, N a power of two so that segment sums are
+// xor shuffles inside the segment); 24, 48 and 64 take one node per wavefront.
+__host__ __device__ constexpr int ens_segs(int n) { return (n == 8 || n == 16 || n == 32) ? 64 / n : 1; }
+
 __host__ __device__ inline int ens_lds_doubles(int n, int nz) {
+    const int segs = ens_segs(n);
     const int nzp = (nz + 1) & ~1;
     const int rs = (n % 4 == 2) ? n : n + 2;
-    return 9 * 64 + n * rs + 4 * 64 + 9 * n + 64 + 2 * nzp + nzp / 2 + 1;
+    return 9 * 64 + segs * n * rs + 4 * 64 + 9 * n * segs + 64 + segs * (2 * nzp + nzp / 2) + 1;
 }
 
-// One wavefront: node `node` of one problem, lane = member.
+// Sum over the aligned group of G lanes (G a power of two dividing 64).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// One wavefront: nodes node0 .. node0 + SEGS - 1 (those < nx * ny) of one
+// problem, a segment of G = 64 / SEGS lanes per node, lane i of a segment =
+// member i; the segment's rows of A and U are its first N lanes.
 template <int N, typename T>
-__device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int max_sweeps) {
+__device__ __forceinline__ void ens_body(const AnalysisParams p, int node0, int max_sweeps) {
+    constexpr int SEGS = ens_segs(N);
+    constexpr int G = kWave / SEGS;
     T* __restrict__ fs = reinterpret_cast<T*>(p.f);
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int nx = p.nx, ny = p.ny, M = p.members;
+    const int plane = nx * ny;
     const int nz = p.nvar * p.lmax;
     const int nzp = (nz + 1) & ~1;
     double* sdx = lds;                   // [9][64]
     constexpr int RS = RowStride<N>::value;
-    double* rows = sdx + 9 * 64;         // [N][RS]  Jacobi rows, then U
-    double* vec = rows + N * RS;         // [4][64]
-    double* se = vec + 4 * 64;           // [9][N]
-    double* zr = se + 9 * N;             // [64]
-    double* sw = zr + 64;                // [nz]
-    double* dt = sw + nzp;               // [nz]
-    int* qx = reinterpret_cast<int*>(dt + nzp);
+    double* rows = sdx + 9 * 64;         // [SEGS][N][RS]  Jacobi rows, then U
+    double* vec = rows + SEGS * N * RS;  // [4][64]
+    double* se = vec + 4 * 64;           // [SEGS][9][N]
+    double* zr = se + 9 * N * SEGS;      // [64]
+    const int seg = lane / G;
+    const int i = lane - seg * G;        // member
+    const int sbase = seg * G;           // first lane of the segment
+    double* sw = zr + 64 + seg * (2 * nzp + nzp / 2);  // this node's [nz] weights
+    double* dt = sw + nzp;                             // [nz] scaled innovations
+    int* qx = reinterpret_cast<int*>(dt + nzp);        // [nz] observation indices
     double2* cs = reinterpret_cast<double2*>(vec);
     double* red = vec + 128;
-    const int x = node % nx, y = node / nx;
-    const bool mem = lane < M;
+    const int node = node0 + seg;
+    const bool here = node < plane;
+    const int x = here ? node % nx : 0, y = here ? node / nx : 0;
+    const bool mem = here && i < M;
 
     double fv[9], xbar[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        fv[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
+        fv[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, i, M), a) : 0.0;
     }
-    if (p.diag_node)
-        node_diag_record(fv, mem, M, node, nx * ny, p.truth_uv,
-                         p.diag_node + (size_t)node * kDiagFieldCount);
+    if (p.diag_node && here)
+        node_diag_record<G>(fv, mem, M, node, plane, p.truth_uv,
+                            p.diag_node + (size_t)node * kDiagFieldCount);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        xbar[a] = wave_sum(fv[a]) / M;
+        xbar[a] = group_sum<G>(fv[a]) / M;
         sdx[a * 64 + lane] = mem ? fv[a] - xbar[a] : 0.0;
     }
-    for (int j = lane; j < nz; j += kWave) {
-        const int slot = j / p.nvar, var = j - slot * p.nvar;
-        const int k = p.loc_pt[(size_t)node * p.lmax + slot];
+    for (int j = i; j < nz; j += G) {
+        const int slot_ = j / p.nvar, var = j - slot_ * p.nvar;
+        const int k = here ? p.loc_pt[(size_t)node * p.lmax + slot_] : -1;
         const int q = k >= 0 ? k * p.nvar + var : 0;
-        const double w = k >= 0 ? sqrt(p.loc_g[(size_t)node * p.lmax + slot] * p.rinv[var]) : 0.0;
+        const double w = k >= 0 ? sqrt(p.loc_g[(size_t)node * p.lmax + slot_] * p.rinv[var]) : 0.0;
         qx[j] = q;
         sw[j] = w;
         dt[j] = w * p.dvec[q];
@@ -189,29 +213,29 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int m
     double S[N], U[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        S[k] = (k == lane) ? p.a : 0.0;
-        U[k] = (k == lane) ? 1.0 : 0.0;
+        S[k] = (k == i) ? p.a : 0.0;
+        U[k] = (k == i) ? 1.0 : 0.0;
     }
     double g = 0.0;
     for (int j = 0; j < nz; ++j) {
-        const double z = mem ? sw[j] * p.dY[(size_t)qx[j] * M + lane] : 0.0;
+        const double z = mem ? sw[j] * p.dY[(size_t)qx[j] * M + i] : 0.0;
         g += z * dt[j];
         wave_lds_sync();
         zr[lane] = z;
         wave_lds_sync();
 #pragma unroll
-        for (int k = 0; k < N; ++k) S[k] += z * zr[k];
+        for (int k = 0; k < N; ++k) S[k] += z * zr[sbase + k];
     }
-    const int sweeps = jacobi_eig<N, 1>(S, U, rows, cs, red, lane, max_sweeps);
+    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, max_sweeps);
     if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
-    const double lam = extract_lane_entry<N>(S, lane);
-    const double psi = lane < N ? 1.0 / lam : 0.0;
-    const double mu = lane < N ? sqrt((M - 1) / lam) : 0.0;
+    const double lam = extract_lane_entry<N>(S, i);
+    const double psi = i < N ? 1.0 / lam : 0.0;
+    const double mu = i < N ? sqrt((M - 1) / lam) : 0.0;
     double* gv = vec;        // g
     wave_lds_sync();
     gv[lane] = g;
-    if (lane < N) {
-        double2* my = reinterpret_cast<double2*>(rows + (size_t)lane * RS);
+    if (i < N) {
+        double2* my = reinterpret_cast<double2*>(rows + (size_t)(seg * N + i) * RS);
 #pragma unroll
         for (int k = 0; k < N / 2; ++k) my[k] = make_double2(U[2 * k], U[2 * k + 1]);
     }
@@ -220,20 +244,20 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int m
     double e[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) e[a] = 0.0;
-    if (lane < N) {
+    if (i < N) {
         for (int k = 0; k < N; ++k) {
-            const double ukc = rows[(size_t)k * RS + lane];
-            t += ukc * gv[k];
+            const double ukc = rows[(size_t)(seg * N + k) * RS + i];
+            t += ukc * gv[sbase + k];
 #pragma unroll
-            for (int a = 0; a < 9; ++a) e[a] += sdx[a * 64 + k] * ukc;
+            for (int a = 0; a < 9; ++a) e[a] += sdx[a * 64 + sbase + k] * ukc;
         }
     }
     double dmean[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) dmean[a] = wave_sum(lane < N ? e[a] * psi * t : 0.0);
-    if (lane < N) {
+    for (int a = 0; a < 9; ++a) dmean[a] = group_sum<G>(i < N ? e[a] * psi * t : 0.0);
+    if (i < N) {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) se[a * N + lane] = e[a] * mu;
+        for (int a = 0; a < 9; ++a) se[(seg * 9 + a) * N + i] = e[a] * mu;
     }
     wave_lds_sync();
     double xa[9];  // the analysis as stored (diagnostics)
@@ -244,22 +268,22 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node, int m
         for (int a = 0; a < 9; ++a) {
             double acc = 0.0;
 #pragma unroll
-            for (int c = 0; c < N; ++c) acc += se[a * N + c] * U[c];
+            for (int c = 0; c < N; ++c) acc += se[(seg * 9 + a) * N + c] * U[c];
             const double v = xbar[a] + dmean[a] + acc;
-            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a, v);
+            PopIO<T>::store(fs + slot(src_node(x, y, a, nx, ny), a, i, M), a, v);
             xa[a] = PopIO<T>::round(v, a);
         }
     }
-    if (p.diag_node)
-        node_diag_record(xa, mem, M, node, nx * ny, p.truth_uv,
-                         p.diag_node + ((size_t)nx * ny + node) * kDiagFieldCount);
+    if (p.diag_node && here)
+        node_diag_record<G>(xa, mem, M, node, plane, p.truth_uv,
+                            p.diag_node + ((size_t)plane + node) * kDiagFieldCount);
 }
 
 template <int N, typename T>
 __global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int max_sweeps) {
-    const int node = xcd_remap(blockIdx.x, gridDim.x);
-    if (node >= p.nx * p.ny) return;
-    ens_body<N, T>(p, node, max_sweeps);
+    const int node0 = xcd_remap(blockIdx.x, gridDim.x) * ens_segs(N);
+    if (node0 >= p.nx * p.ny) return;
+    ens_body<N, T>(p, node0, max_sweeps);
 }
 
 // Batched form: wavefront w takes waves[w] = (problem, node).
@@ -269,7 +293,7 @@ __global__ __launch_bounds__(64) void analysis_ens_batch_kernel(const AnalysisPa
                                                                 int max_sweeps) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     if (w >= nwaves) return;
-    const int2 d = waves[w];
+    const int2 d = waves[w];  // (problem, first node of the wavefront's ens_segs(N) nodes)
     ens_body<N, T>(P[d.x], d.y, max_sweeps);
 }
 
@@ -442,7 +466,7 @@ hipError_t launch_ens_t(const AnalysisParams& p, hipStream_t s) {
                                            (int)bytes);
         if (e != hipSuccess) return e;
     }
-    analysis_ens_kernel<N, T><<<plane, 64, bytes, s>>>(p, 30);
+    analysis_ens_kernel<N, T><<<(plane + ens_segs(N) - 1) / ens_segs(N), 64, bytes, s>>>(p, 30);
     return hipGetLastError();
 }
 
@@ -508,6 +532,8 @@ int ens_size_for(int n) {
 }
 
 int ens_lds_bytes(int n, int nz) { return ens_lds_doubles(n, nz) * (int)sizeof(double); }
+
+int ens_segments(int n) { return ens_segs(n); }
 
 hipError_t launch_observe(const void* f, const int* pts, int npts, int nvar, double* yf,
                           LbmDims d, int storage, hipStream_t s) {
