@@ -60,29 +60,30 @@ struct RowStride {
 };
 
 // Rotation (c, s) that annihilates a_pq of the 2 x 2 block [[a_pp, a_pq], [a_pq, a_qq]]
-// (c = s = 1, 0 for a_pq = 0).  t = sgn(tau) / (|tau| + sqrt(1 + tau^2)),
+// (c = 1, s = 0 for a_pq = 0 or when `use` is false).
+// t = sgn(tau) / (|tau| + sqrt(1 + tau^2)),
 // tau = (a_qq - a_pp) / (2 a_pq), the smaller root of t^2 + 2 tau t - 1 = 0, is
 // evaluated in FP32 on operands scaled so that |a_pq| is near [1, 2): any t gives
 // an exactly orthogonal rotation through c and s below (FP64), and an
 // FP32-accurate t still removes all but ~1e-7 of a_pq, which the next sweeps
-// finish.
-__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double* cp,
-                                                double* sp) {
-    double c = 1.0, s = 0.0;
-    if (apq != 0.0) {
-        const double d = aqq - app;
-        const double sc = ldexp(1.0, -max(ilogb(apq), -1000));
-        const float af = (float)(apq * sc);
-        const float at = fabsf((float)(d * sc)) * 0.5f * __builtin_amdgcn_rcpf(fabsf(af));
-        float tf = at > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(at)
-                              : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(1.0f + at * at));
-        if ((d < 0.0) != (apq < 0.0)) tf = -tf;
-        const double t = (double)tf;
-        c = rsqrt(1.0 + t * t);
-        s = t * c;
-    }
-    *cp = c;
-    *sp = s;
+// finish.  Branch-free: for a_pq = 0 the intermediate t is inf or NaN and the
+// final select discards it, so the three operand loads of a caller issue
+// together instead of waiting on a test of a_pq.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, bool use,
+                                                double* cp, double* sp) {
+    const double d = aqq - app;
+    const double sc = ldexp(1.0, -max(ilogb(apq), -1000));
+    const float af = (float)(apq * sc);
+    const float at = fabsf((float)(d * sc)) * 0.5f * __builtin_amdgcn_rcpf(fabsf(af));
+    // |tau| + sqrt(1 + tau^2), or 2 |tau| where tau^2 would overflow
+    const float den = at > 1e18f ? at + at : at + __builtin_amdgcn_sqrtf(1.0f + at * at);
+    float tf = __builtin_amdgcn_rcpf(den);
+    if ((d < 0.0) != (apq < 0.0)) tf = -tf;
+    const double t = (double)tf;
+    const double c = rsqrt(1.0 + t * t);
+    const bool rot = use && apq != 0.0;
+    *cp = rot ? c : 1.0;
+    *sp = rot ? t * c : 0.0;
 }
 
 template <int N, int SEGS, int P>
@@ -105,11 +106,11 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
     const bool first = ((i - P) & 1) == 0;
     const int pi = first ? i + 1 : i - 1;
     const bool paired = active && pi >= 0 && pi < N;
-    const int p = first ? i : pi;
-    double c = 1.0, s = 0.0;
-    if (paired)
-        jacobi_rotation(segrows[(size_t)p * RS + p], segrows[(size_t)(p + 1) * RS + p + 1],
-                        segrows[(size_t)p * RS + p + 1], &c, &s);
+    // a lane without a partner reads the first pair's block and discards it
+    const int p = paired ? (first ? i : pi) : 0;
+    double c, s;
+    jacobi_rotation(segrows[(size_t)p * RS + p], segrows[(size_t)(p + 1) * RS + p + 1],
+                    segrows[(size_t)p * RS + p + 1], paired, &c, &s);
     cs[lane] = make_double2(c, s);
     wave_lds_sync();
     // S <- P^T J^T S J P and U <- U J P, one double2 of the row at a time, so

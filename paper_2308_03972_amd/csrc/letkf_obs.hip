@@ -200,12 +200,11 @@ __device__ __forceinline__ void split_round(double (&S)[N / 2], double (&U)[N / 
     const bool first = ((i - P) & 1) == 0;
     const int pi = first ? i + 1 : i - 1;
     const bool paired = active && pi >= 0 && pi < N;
-    double c = 1.0, s = 0.0;
-    if (paired) {
-        const int p = first ? i : pi;
-        jacobi_rotation(rows[(size_t)p * RS + p], rows[(size_t)(p + 1) * RS + p + 1],
-                        rows[(size_t)p * RS + p + 1], &c, &s);
-    }
+    // a thread without a partner reads the first pair's block and discards it
+    const int p = paired ? (first ? i : pi) : 0;
+    double c, s;
+    jacobi_rotation(rows[(size_t)p * RS + p], rows[(size_t)(p + 1) * RS + p + 1],
+                    rows[(size_t)p * RS + p + 1], paired, &c, &s);
     if (active) csw[i] = make_double2(c, s);
     wave_lds_sync();
     const double sg = first ? s : -s;
