@@ -93,6 +93,18 @@ def cpu_baseline(cfg, force, pts, sample_steps: int, sample_nodes: int):
     t_node = (time.perf_counter() - t0) / sample_nodes
     t_cycle = cfg.steps_per_cycle * t_step + cfg.n * cfg.n * t_node
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same LBM steps on one thread (the analysis sample runs on one already)
+    t_step1 = None
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        oracle.lbm_steps(fe, 1, cfg.tau0, cfg.cs, force, cfg.mu)
+        t_step1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+    except OSError:
+        pass
     return {
         "value": 1.0 / t_cycle, "unit": "cycles/s", "cores": threads, "kind": "oracle",
         "sample": (f"{sample_steps} oracle LBM steps of the full {cfg.n}^2 x {cfg.members} "
@@ -100,7 +112,108 @@ def cpu_baseline(cfg, force, pts, sample_steps: int, sample_nodes: int):
                    f"{sample_nodes} of {cfg.n * cfg.n} nodes (NumPy/LAPACK eigh), scaled to "
                    f"{cfg.steps_per_cycle} steps + {cfg.n * cfg.n} nodes per cycle"),
         "s_per_lbm_step": t_step, "s_per_node_analysis": t_node,
+        "s_per_lbm_step_1_thread": t_step1,
     }
+
+
+def observations(cfg, tctx, total: int):
+    """Truth run (M = 1 context) and the observation sets of `total` cycles,
+    resident on the GPU: y_o per cycle and the truth velocity per cycle."""
+    import torch
+    from paper_2308_03972_amd import binding, inputs
+    dev = torch.device("cuda:0")
+    cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    truth_uv, _ = inputs.initial_velocities(cfg)
+    noise = cuda(inputs.all_observation_noise(cfg, total))
+    sig = cuda(inputs.sigma_vector(cfg))
+    ft = tctx.init_equilibrium(cuda(truth_uv[None]))
+    yo_all = torch.empty((total, cfg.n_obs), dtype=torch.float64, device=dev)
+    tuv_all = torch.empty((total, 2, cfg.n, cfg.n), dtype=torch.float64, device=dev)
+    for c in range(total):
+        tctx.step(ft, cfg.steps_per_cycle)
+        ytrue = tctx.observe(ft)[0].contiguous()
+        yo_all[c] = binding.synth_obs(ytrue, noise[c].contiguous(), sig)
+        tuv_all[c] = tctx.moments(ft)[0, 1:]
+    torch.cuda.synchronize()
+    return yo_all, tuv_all
+
+
+def run_form(ctx, cfg, yo_all, tuv_all, warmup: int, steps: int, repeats: int = 1,
+             breakdown_cycles: int = 5):
+    """Warmup + timed cycles of one form, `repeats` times from the same initial
+    ensemble.  Returns per repeat (elapsed s, diagnostics of the timed cycles,
+    stage ms and launch counts of the timed region) and the stage ms per cycle of
+    a per-launch pass after the last repeat."""
+    import torch
+    from paper_2308_03972_amd import binding, inputs
+    dev = torch.device("cuda:0")
+    _, mem_uv = inputs.initial_velocities(cfg)
+    mem = torch.from_numpy(np.ascontiguousarray(mem_uv, dtype=np.float64)).to(dev)
+    s, total = cfg.steps_per_cycle, warmup + steps
+    runs = []
+    for _ in range(repeats):
+        diag = torch.zeros((total, 2 * binding.DIAG_LEN), dtype=torch.float64, device=dev)
+        fe = ctx.init_equilibrium(mem)
+        for c in range(warmup):
+            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
+        torch.cuda.synchronize()
+        # timed region: HIP events on the launch stream around each cycle's
+        # forecast steps and around each analysis (level 2: one pair each)
+        ctx.set_profiling(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(warmup, total):
+            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms, n = ctx.profile_collect()
+        ctx.set_profiling(False)
+        runs.append((el, diag[warmup:].cpu().numpy(), ms, n))
+    # stage breakdown: a few more cycles with an event pair around every launch
+    scratch = torch.zeros(2 * binding.DIAG_LEN, dtype=torch.float64, device=dev)
+    ctx.set_profiling(True)
+    for c in range(total - breakdown_cycles, total):
+        ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], scratch)
+    ms1, _ = ctx.profile_collect()
+    ctx.set_profiling(False)
+    breakdown = {binding.STAGES[k]: round(ms1[k] / breakdown_cycles, 4)
+                 for k in range(binding.NSTAGES)}
+    return runs, breakdown
+
+
+def median_run(runs):
+    """The repeat with the median elapsed time."""
+    return sorted(runs, key=lambda r: r[0])[len(runs) // 2]
+
+
+def precision_config_form(warmup: int, steps: int):
+    """The precision form at its own configuration (512^2, 64 members, 16x16
+    (u, v) observations, s = 20) against the plain FP64 form on the same
+    observations: cycles/s of both and the analysis RMSE difference."""
+    from paper_2308_03972_amd import binding, inputs
+    import torch
+    cfg = inputs.CONFIGS["precision"]
+    dev = torch.device("cuda:0")
+    force = torch.from_numpy(np.ascontiguousarray(inputs.body_force(cfg))).to(dev)
+    tctx = binding.Context.from_config(cfg, members=1, force=force)
+    yo_all, tuv_all = observations(cfg, tctx, warmup + steps)
+    out = {"workload": (f"{cfg.n}x{cfg.n}, {cfg.members} members, {cfg.obs_side}x{cfg.obs_side} "
+                        f"(u,v) observations, s={cfg.steps_per_cycle}, r={cfg.loc_r:g}")}
+    res = {}
+    for name, storage in (("plain", binding.STORAGE_F64), ("f32_dev", binding.STORAGE_F32_DEV)):
+        ctx = binding.Context.from_config(cfg, force=force, storage=storage)
+        runs, _ = run_form(ctx, cfg, yo_all, tuv_all, warmup, steps, 1, breakdown_cycles=1)
+        el, d, ms, n = runs[0]
+        res[name] = (el, d)
+        out[f"{name}_cycles_per_s"] = round(steps / el, 3)
+        out[f"{name}_stream_collide_avg_us"] = round(1e3 * ms[0] / max(n[0], 1), 2)
+        ctx.close()
+    out["speedup_vs_plain"] = round(res["plain"][0] / res["f32_dev"][0], 4)
+    out["max_abs_rmse_a_diff_vs_plain"] = float(np.max(np.abs(
+        res["f32_dev"][1][:, binding.DIAG_LEN] - res["plain"][1][:, binding.DIAG_LEN])))
+    out["tolerance_1e-3_sigma"] = 1e-3 * cfg.sigma
+    tctx.close()
+    return out
 
 
 def differentiation_form(reps: int, storage: int):
@@ -277,6 +390,10 @@ def main() -> int:
                     help="timed cycles of the batching form")
     ap.add_argument("--grad-reps", type=int, default=20,
                     help="timed misfit gradients of the differentiation form")
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed runs of the plain and precision forms (value: the median)")
+    ap.add_argument("--precision-cycles", type=int, default=30,
+                    help="timed cycles of each form at the precision configuration (512^2)")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--cpu-nodes", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -310,7 +427,6 @@ def main() -> int:
     cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
 
     # ---- inputs: seeded fields, force, observing network --------------------
-    truth_uv, mem_uv = inputs.initial_velocities(cfg)
     force_np = inputs.body_force(cfg)
     pts = inputs.observation_points(cfg)
     force = cuda(force_np)
@@ -320,56 +436,23 @@ def main() -> int:
         f"{ectx.eig_size}, max local points {ectx.max_local_points}")
 
     # ---- truth run and observations, all resident before timing -------------
-    noise = cuda(inputs.all_observation_noise(cfg, total))
-    sig = cuda(inputs.sigma_vector(cfg))
-    ft = tctx.init_equilibrium(cuda(truth_uv[None]))
-    yo_all = torch.empty((total, cfg.n_obs), dtype=torch.float64, device=dev)
-    tuv_all = torch.empty((total, 2, cfg.n, cfg.n), dtype=torch.float64, device=dev)
-    for c in range(total):
-        tctx.step(ft, s)
-        ytrue = tctx.observe(ft)[0].contiguous()
-        yo_all[c] = binding.synth_obs(ytrue, noise[c].contiguous(), sig)
-        tuv_all[c] = tctx.moments(ft)[0, 1:]
-    torch.cuda.synchronize()
+    yo_all, tuv_all = observations(cfg, tctx, total)
     log(f"truth and {total} observation sets ready")
 
-    def run_form(ctx):
-        """Warmup + timed cycles of one form; returns (elapsed s, diag, stage ms and
-        counts of the timed region, stage ms per cycle of a per-launch pass)."""
-        diag = torch.zeros((total, 2 * binding.DIAG_LEN), dtype=torch.float64, device=dev)
-        fe = ctx.init_equilibrium(cuda(mem_uv))
-        for c in range(args.warmup):
-            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
-        torch.cuda.synchronize()
-        # timed region: HIP events on the launch stream around each cycle's
-        # forecast steps and around each analysis (level 2: one pair each)
-        ctx.set_profiling(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for c in range(args.warmup, total):
-            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], diag[c])
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        ms, n = ctx.profile_collect()
-        ctx.set_profiling(False)
-        # stage breakdown: five more cycles with an event pair around every launch
-        scratch = torch.zeros(2 * binding.DIAG_LEN, dtype=torch.float64, device=dev)
-        ctx.set_profiling(True)
-        for c in range(total - 5, total):
-            ctx.run_cycle(fe, s, yo_all[c], tuv_all[c], scratch)
-        ms1, n1 = ctx.profile_collect()
-        ctx.set_profiling(False)
-        breakdown = {binding.STAGES[k]: round(ms1[k] / 5, 4) for k in range(binding.NSTAGES)}
-        return el, diag[args.warmup:].cpu().numpy(), ms, n, breakdown
-
-    elapsed, d, stage_ms, stage_n, breakdown = run_form(ectx)
-    log(f"plain form: timed {args.steps} cycles in {elapsed:.3f} s")
+    runs, breakdown = run_form(ectx, cfg, yo_all, tuv_all, args.warmup, args.steps, args.repeats)
+    elapsed, d, stage_ms, stage_n = median_run(runs)
+    log(f"plain form: timed {args.steps} cycles in " + ", ".join(f"{r[0]:.3f}" for r in runs)
+        + f" s (median {elapsed:.3f} s)")
     forms = {}
     if not args.no_forms:
         f32ctx = binding.Context.from_config(cfg, force=force, route=route,
                                              storage=binding.STORAGE_F32_DEV)
-        el32, d32, ms32, n32, _ = run_form(f32ctx)
-        log(f"precision form: timed {args.steps} cycles in {el32:.3f} s")
+        runs32, _ = run_form(f32ctx, cfg, yo_all, tuv_all, args.warmup, args.steps, args.repeats)
+        el32, d32, ms32, n32 = median_run(runs32)
+        log(f"precision form: timed {args.steps} cycles in {el32:.3f} s (median)")
+        log("precision form at its own configuration (512^2)")
+        forms["f32_dev_512"] = precision_config_form(5, args.precision_cycles)
+        log(f"precision form at 512^2: {forms['f32_dev_512']['speedup_vs_plain']}x plain")
         log("batching form: twelve problems")
         forms["batching"] = batching_form(args.batch_cycles, 3)
         log(f"batching: {forms['batching']['cycles_per_s']} cycles/s "
@@ -443,7 +526,9 @@ def main() -> int:
             "obs_points": cfg.n_points, "route": ["", "ensemble", "observation"][ectx.route],
             "eig_size": ectx.eig_size,
         },
+        "repeats_cycles_per_s": [round(args.steps / r[0], 3) for r in runs],
         "glups_member": round(glups, 3),
+        "glups_member_stream_collide": round(plane * cfg.members / t_lbm / 1e9, 3),
         "rmse_a_mean": float(rmse_a.mean()),
         "rmse_f_mean": float(rmse_f.mean()),
         "obs_noise_rms": cfg.sigma * math.sqrt(2.0),
