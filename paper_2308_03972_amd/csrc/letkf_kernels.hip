@@ -217,14 +217,27 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node0, int 
         U[k] = (k == i) ? 1.0 : 0.0;
     }
     double g = 0.0;
-    for (int j = 0; j < nz; ++j) {
-        const double z = mem ? sw[j] * p.dY[(size_t)qx[j] * M + i] : 0.0;
-        g += z * dt[j];
-        wave_lds_sync();
-        zr[lane] = z;
-        wave_lds_sync();
+    // the perturbations are loaded eight observations at a time, unconditionally
+    // (a non-member lane reads member 0), so that the loads of a chunk are in
+    // flight together; the sums run in observation order
+    constexpr int kZc = 8;
+    for (int j0 = 0; j0 < nz; j0 += kZc) {
+        double zc[kZc];
 #pragma unroll
-        for (int k = 0; k < N; ++k) S[k] += z * zr[sbase + k];
+        for (int t = 0; t < kZc; ++t)
+            zc[t] = p.dY[(size_t)qx[min(j0 + t, nz - 1)] * M + (mem ? i : 0)];
+#pragma unroll
+        for (int t = 0; t < kZc; ++t) {
+            const int j = j0 + t;
+            if (j >= nz) break;  // uniform over the wavefront
+            const double z = mem ? sw[j] * zc[t] : 0.0;
+            g += z * dt[j];
+            wave_lds_sync();
+            zr[lane] = z;
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < N; ++k) S[k] += z * zr[sbase + k];
+        }
     }
     const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, max_sweeps);
     if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);

@@ -98,10 +98,14 @@ __device__ __forceinline__ void eig_body(const AnalysisParams p, const int* node
     {
         const double wi = active ? sw[lane] : 0.0;
         const double* Krow = p.K + (size_t)(active ? qx[lane] : 0) * p.nobs;
+        // unconditional loads (an unused entry has index 0), so that all N are
+        // in flight together; the weights select afterwards
+#pragma unroll
+        for (int k = 0; k < N; ++k) S[k] = Krow[qx[sbase + k]];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const double wk = sw[sbase + k];
-            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * Krow[qx[sbase + k]] : 0.0;
+            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * S[k] : 0.0;
             U[k] = (k == i && active) ? 1.0 : 0.0;
         }
     }
@@ -294,10 +298,13 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
     {
         const double wi = active ? sw[i] : 0.0;
         const double* Krow = p.K + (size_t)(active ? qx[i] : 0) * p.nobs;
+        // unconditional loads (an unused entry has index 0), all in flight together
+#pragma unroll
+        for (int k = 0; k < H; ++k) S[k] = Krow[qx[c0 + k]];
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             const double wk = sw[c0 + k];
-            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * Krow[qx[c0 + k]] : 0.0;
+            S[k] = (wi != 0.0 && wk != 0.0) ? wi * wk * S[k] : 0.0;
             U[k] = (active && c0 + k == i) ? 1.0 : 0.0;
         }
     }
@@ -566,12 +573,15 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
 #pragma unroll
     for (int a = 0; a < 9; ++a) xa[a] = 0.0;
     if (mem) {
-        // this member's l observation perturbations, loaded together
+        // this member's l observation perturbations: unconditional loads (an
+        // unused entry has index 0) so that all N are in flight together
         double z[N];
+#pragma unroll
+        for (int jj = 0; jj < N; ++jj) z[jj] = p.dY[(size_t)qx[jj] * M + lane];
 #pragma unroll
         for (int jj = 0; jj < N; ++jj) {
             const double wj = sw[jj];
-            z[jj] = wj != 0.0 ? wj * p.dY[(size_t)qx[jj] * M + lane] : 0.0;
+            z[jj] = wj != 0.0 ? wj * z[jj] : 0.0;
         }
         double acc[9];
 #pragma unroll
