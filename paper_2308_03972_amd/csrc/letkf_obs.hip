@@ -485,22 +485,31 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
     const bool mem = lane < M;
     const int x = node % nx, y = node / nx;
 
-    // independent loads first: the nine populations, G and h, the local observations
+    // independent loads first, in one block so that they are all in flight
+    // before the first use: the nine populations, G and h (the last pass
+    // clamps its index), this lane's local observation
+    constexpr int kGn = n * n + n;
+    constexpr int kGp = (kGn + kWave - 1) / kWave;
     double dx[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a)
         dx[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
+    const double* g = gin + (size_t)item * kGn;
+    double gv[kGp];
+#pragma unroll
+    for (int u = 0; u < kGp; ++u) gv[u] = g[min(lane + u * kWave, kGn - 1)];
+    int qj = 0;
+    double wj = 0.0;
+    if (lane < n) local_obs(p, node, lane, &qj, &wj, nullptr);
     if (p.diag_node)
         node_diag_record(dx, mem, M, node, nx * ny, p.truth_uv,
                          p.diag_node + (size_t)node * kDiagFieldCount);
-    const double* g = gin + (size_t)item * (n * n + n);
-    for (int t = lane; t < n * n + n; t += kWave) Gs[t] = g[t];
-    for (int j = lane; j < n; j += kWave) {
-        int q;
-        double w;
-        local_obs(p, node, j, &q, &w, nullptr);
-        qx[j] = q;
-        sw[j] = w;
+#pragma unroll
+    for (int u = 0; u < kGp; ++u)
+        if (lane + u * kWave < kGn) Gs[lane + u * kWave] = gv[u];
+    if (lane < n) {
+        qx[lane] = qj;
+        sw[lane] = wj;
     }
     wave_lds_sync();
     // x_bar and dX of the nine populations
