@@ -7,11 +7,58 @@
 namespace lbmletkf {
 namespace dev {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+// ---------------------------------------------------------------------------
+// reductions over aligned groups of G lanes (G a power of two <= 64), on the
+// VALU: a butterfly inside each row of 16 lanes with DPP moves (xor 1 and
+// xor 2 as quad permutations; then the half-row and row mirrors, which pair
+// the same quads and half-rows as xor 4 and xor 8 once every quad, then every
+// half-row, holds one value), and for G = 32, 64 the row results read with
+// v_readlane and combined in a fixed order.  Every lane of a group gets the
+// same bits.  Call in wave-uniform control flow (all 64 lanes active).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x) {
+    // every source lane of these patterns lies in the row, so bound_ctrl (zero
+    // for an out-of-row source) never applies; it spares initialising the result
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
 }
+
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+template <int G, typename Op>
+__device__ __forceinline__ double group_reduce(double x, Op op) {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group size must be a power of two");
+    if (G >= 2) x = op(x, dpp_partner<0xB1>(x));   // quad_perm [1, 0, 3, 2]
+    if (G >= 4) x = op(x, dpp_partner<0x4E>(x));   // quad_perm [2, 3, 0, 1]
+    if (G >= 8) x = op(x, dpp_partner<0x141>(x));  // row_half_mirror
+    if (G >= 16) x = op(x, dpp_partner<0x140>(x)); // row_mirror
+    if (G == 32) {
+        const double lo = op(lane_value(x, 0), lane_value(x, 16));
+        const double hi = op(lane_value(x, 32), lane_value(x, 48));
+        x = (threadIdx.x & 32) ? hi : lo;
+    } else if (G == 64) {
+        x = op(op(op(lane_value(x, 0), lane_value(x, 16)), lane_value(x, 32)), lane_value(x, 48));
+    }
+    return x;
+}
+
+struct OpAdd {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMin {
+    __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMax {
+    __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+
+__device__ __forceinline__ double wave_sum(double v) { return group_reduce<kWave>(v, OpAdd()); }
 
 // Order this wave's LDS writes before its later LDS reads (cross-lane).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -207,11 +254,7 @@ __device__ __forceinline__ void node_diag_record(const double (&f)[9], bool mem,
         rmin = rho;
         rmax = rho;
     }
-    auto gsum = [](double x) {
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-        return x;
-    };
+    auto gsum = [](double x) { return group_reduce<G>(x, OpAdd()); };
     const double ub = gsum(u) / M, vb = gsum(v) / M;
     double err2 = 0.0, spr2 = 0.0;
     if (truth_uv) {
@@ -223,11 +266,8 @@ __device__ __forceinline__ void node_diag_record(const double (&f)[9], bool mem,
         spr2 = gsum(du * du + dv * dv) / (M - 1);
     }
     bad = gsum(bad);
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-        rmin = fmin(rmin, __shfl_xor(rmin, off, kWave));
-        rmax = fmax(rmax, __shfl_xor(rmax, off, kWave));
-    }
+    rmin = group_reduce<G>(rmin, OpMin());
+    rmax = group_reduce<G>(rmax, OpMax());
     if (threadIdx.x % G == 0) {
         out[0] = err2;
         out[1] = spr2;

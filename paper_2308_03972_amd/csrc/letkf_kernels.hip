@@ -148,9 +148,7 @@ __host__ __device__ inline int ens_lds_doubles(int n, int nz) {
 // Sum over the aligned group of G lanes (G a power of two dividing 64).
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    return group_reduce<G>(v, OpAdd());
 }
 
 // One wavefront: nodes node0 .. node0 + SEGS - 1 (those < nx * ny) of one
@@ -363,10 +361,8 @@ __global__ __launch_bounds__(kDiagBlock) void diag_partial_kernel(
     }
     // combine: lanes of each wave, then the waves in a fixed order
     bad = wave_sum(bad);
-    for (int off = 32; off > 0; off >>= 1) {
-        rmin = fmin(rmin, __shfl_xor(rmin, off, kWave));
-        rmax = fmax(rmax, __shfl_xor(rmax, off, kWave));
-    }
+    rmin = group_reduce<kWave>(rmin, OpMin());
+    rmax = group_reduce<kWave>(rmax, OpMax());
     __shared__ double red[kDiagFields][kDiagWaves];
     if (lane == 0) {
         red[0][wave] = err2;
