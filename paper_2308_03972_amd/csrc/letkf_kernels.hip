@@ -185,10 +185,14 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node0, int 
     const bool mem = here && i < M;
 
     double fv[9], xbar[9];
+    // unconditional loads (a lane past the ensemble or the grid reads member 0
+    // of node 0 and discards it), so that the nine are in flight together
+    const int mi = mem ? i : 0;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        fv[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, i, M), a) : 0.0;
-    }
+    for (int a = 0; a < 9; ++a)
+        fv[a] = PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, mi, M), a);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fv[a] = mem ? fv[a] : 0.0;
     if (p.diag_node && here)
         node_diag_record<G>(fv, mem, M, node, plane, p.truth_uv,
                             p.diag_node + (size_t)node * kDiagFieldCount);

@@ -491,9 +491,12 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
     constexpr int kGn = n * n + n;
     constexpr int kGp = (kGn + kWave - 1) / kWave;
     double dx[9];
+    const int ml = mem ? lane : 0;  // a lane past the ensemble reads member 0 and discards it
 #pragma unroll
     for (int a = 0; a < 9; ++a)
-        dx[a] = mem ? PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a) : 0.0;
+        dx[a] = PopIO<T>::load(fs + slot(src_node(x, y, a, nx, ny), a, ml, M), a);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) dx[a] = mem ? dx[a] : 0.0;
     const double* g = gin + (size_t)item * kGn;
     double gv[kGp];
 #pragma unroll
