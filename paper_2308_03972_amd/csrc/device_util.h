@@ -155,6 +155,14 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
     const bool paired = active && pi >= 0 && pi < N;
     // a lane without a partner reads the first pair's block and discards it
     const int p = paired ? (first ? i : pi) : 0;
+    const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)(paired ? pi : i) * RS);
+    // the first four slices of the partner's row are read with the block, so
+    // that their latency hides behind the rotation's arithmetic (N = 24: 169 ->
+    // 167 VGPRs, three wavefronts per SIMD instead of two)
+    constexpr int KP = N / 2 < 4 ? N / 2 : 4;
+    double2 pre[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) pre[k] = pr[k];
     double c, s;
     jacobi_rotation(segrows[(size_t)p * RS + p], segrows[(size_t)(p + 1) * RS + p + 1],
                     segrows[(size_t)p * RS + p + 1], paired, &c, &s);
@@ -166,11 +174,10 @@ __device__ __forceinline__ void jacobi_round(double (&S)[N], double (&U)[N], dou
     // lane without a partner takes its own row with c = 1, s = 0, which leaves
     // it unchanged), then the column rotation of each pair (r, r+1) whose two
     // entries are mixed, by the pair's (c, s)
-    const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)(paired ? pi : i) * RS);
     const double sg = first ? s : -s;
 #pragma unroll
     for (int k = 0; k < N / 2; ++k) {
-        const double2 v = pr[k];
+        const double2 v = k < KP ? pre[k < KP ? k : 0] : pr[k];
         S[2 * k] = c * v.x + sg * S[2 * k];
         S[2 * k + 1] = c * v.y + sg * S[2 * k + 1];
         const int r = 2 * k - P;
