@@ -223,18 +223,18 @@ int even_up(int n) { return (n + 1) & ~1; }
 // Only the ratios between entries are used.
 double obs_node_cost(int n) {
     switch (n) {
-        case 8: return 7;     case 10: return 9;    case 12: return 13;   case 14: return 17;
-        case 16: return 21;   case 18: return 30;   case 20: return 36;   case 22: return 57;
-        case 24: return 73;   case 26: return 84;   case 28: return 96;   case 30: return 107;
-        case 32: return 118;  case 40: return 420;  case 48: return 710;  case 56: return 1130;
-        default: return 1500;
+        case 8: return 6;     case 10: return 8;    case 12: return 11;   case 14: return 16;
+        case 16: return 19;   case 18: return 28;   case 20: return 32;   case 22: return 56;
+        case 24: return 65;   case 26: return 77;   case 28: return 88;   case 30: return 99;
+        case 32: return 109;  case 40: return 404;  case 48: return 687;  case 56: return 1064;
+        default: return 1466;
     }
 }
 
 double ens_node_cost(int n) {
     switch (n) {
-        case 8: return 3.4;   case 16: return 16.4; case 24: return 121;
-        case 32: return 145;  case 48: return 747;  default: return 2052;
+        case 8: return 3.0;   case 16: return 15.6; case 24: return 125;
+        case 32: return 133;  case 48: return 718;  default: return 1731;
     }
 }
 
