@@ -586,12 +586,19 @@ lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* st
     void* a = d_f;
     void* b = c->fbuf();
     StageTimer all(c, kStageCollide, s, kPerCall, nsteps);
-    for (int k = 0; k < nsteps; ++k) {
-        StageTimer t(c, kStageCollide, s);
-        hipError_t e = launch_stream_collide(a, b, c->force(), c->dims, c->lbm.tau0, c->lbm.cs,
-                                             c->lbm.mu, c->storage(), s);
+    // pairs of steps in one launch where the ensemble allows it, a single step
+    // for an odd remainder
+    const bool two = two_step_supported(c->dims, c->storage());
+    for (int k = 0; k < nsteps;) {
+        const int n = (two && nsteps - k >= 2) ? 2 : 1;
+        StageTimer t(c, kStageCollide, s, kPerLaunch, n);
+        hipError_t e = n == 2 ? launch_stream_collide2(a, b, c->force(), c->dims, c->lbm.tau0,
+                                                       c->lbm.cs, c->lbm.mu, c->storage(), s)
+                              : launch_stream_collide(a, b, c->force(), c->dims, c->lbm.tau0,
+                                                      c->lbm.cs, c->lbm.mu, c->storage(), s);
         if (e != hipSuccess) return hip_fail(e, "stream_collide");
         std::swap(a, b);
+        k += n;
     }
     if (a != d_f) {
         hipError_t e = hipMemcpyAsync(d_f, a, c->state_bytes(), hipMemcpyDeviceToDevice, s);

@@ -86,6 +86,12 @@ struct LbmDims {
 // `storage` selects the element type of every state buffer (Storage).
 hipError_t launch_stream_collide(const void* fin, void* fout, const double* force, LbmDims d,
                                  double tau0, double cs, double mu, int storage, hipStream_t s);
+// Two such steps in one launch (spatial tiles with a recomputed one-node ring,
+// the intermediate state in LDS); needs two_step_supported(d).  Same
+// arithmetic and rounding as two launches of launch_stream_collide.
+bool two_step_supported(LbmDims d, int storage);
+hipError_t launch_stream_collide2(const void* fin, void* fout, const double* force, LbmDims d,
+                                  double tau0, double cs, double mu, int storage, hipStream_t s);
 // One problem of a batched forecast step: its state buffers (storage layout),
 // force, sizes, relaxation parameters and its first tile in the batch.
 struct LbmTask {

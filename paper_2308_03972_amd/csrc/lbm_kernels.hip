@@ -29,31 +29,36 @@ constexpr int kBlock = 256;
 __device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 
-// Relax one node: f[9] in (pre-collision), f*[9] out.
+// Relax one node: f[9] in (pre-collision), f*[9] out.  The multiply-adds are
+// written out as fma() and the compiler may fuse nothing else, so the result
+// does not depend on the code the function is inlined into: the one-step and
+// the two-step kernels give the same bits.
 __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double smag,
                                              double fx_ext, double fy_ext, double mu) {
+#pragma clang fp contract(off)
     const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const double jx = (f[1] - f[2]) + (f[5] - f[6]) + (f[7] - f[8]);
     const double jy = (f[3] - f[4]) + (f[5] - f[6]) + (f[8] - f[7]);
     const double inv_rho = 1.0 / rho;
     const double u = jx * inv_rho, v = jy * inv_rho;
     const double uu = u * u, vv = v * v, uv = u * v;
-    // non-equilibrium momentum flux
-    const double pxx = (f[1] + f[2] + f[5] + f[6] + f[7] + f[8]) - rho * (1.0 / 3.0 + uu);
-    const double pyy = (f[3] + f[4] + f[5] + f[6] + f[7] + f[8]) - rho * (1.0 / 3.0 + vv);
-    const double pxy = (f[5] + f[6] - f[7] - f[8]) - rho * uv;
-    const double pn = sqrt(pxx * pxx + pyy * pyy + 2.0 * pxy * pxy);
-    const double tau = 0.5 * (tau0 + sqrt(tau0 * tau0 + smag * pn * inv_rho));
+    // non-equilibrium momentum flux: sum c c f - rho/3 I - rho u u
+    const double pxx = fma(-rho, 1.0 / 3.0 + uu, f[1] + f[2] + f[5] + f[6] + f[7] + f[8]);
+    const double pyy = fma(-rho, 1.0 / 3.0 + vv, f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
+    const double pxy = fma(-rho, uv, f[5] + f[6] - f[7] - f[8]);
+    const double pn = sqrt(fma(pxx, pxx, fma(pyy, pyy, (2.0 * pxy) * pxy)));
+    const double tau = 0.5 * (tau0 + sqrt(fma(tau0, tau0, (smag * pn) * inv_rho)));
     const double omega = 1.0 / tau;
     // acceleration: external field plus linear friction
-    const double gx = fx_ext - mu * u, gy = fy_ext - mu * v;
-    const double usq = 1.5 * (uu + vv);
+    const double gx = fma(-mu, u, fx_ext), gy = fma(-mu, v, fy_ext);
+    const double one_usq = 1.0 - 1.5 * (uu + vv);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const double cu = cx_of(a) * u + cy_of(a) * v;
-        const double feq = rho * w_of(a) * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
-        const double Fa = 3.0 * w_of(a) * rho * (cx_of(a) * gx + cy_of(a) * gy);
-        f[a] = f[a] - omega * (f[a] - feq) + Fa;
+        // f^eq = rho w (1 + 3 cu + 4.5 cu^2 - 1.5 u.u)
+        const double feq = (rho * w_of(a)) * fma(cu, fma(4.5, cu, 3.0), one_usq);
+        const double Fa = (3.0 * w_of(a) * rho) * (cx_of(a) * gx + cy_of(a) * gy);
+        f[a] = fma(-omega, f[a] - feq, f[a] + Fa);
     }
 }
 
@@ -161,6 +166,62 @@ __global__ __launch_bounds__(kBlock) void stream_collide_batch_kernel(const LbmT
                                  tk.nx, tk.ny, M, node, m, tk.tau0, tk.smag, tk.mu);
         }
     }
+}
+
+// Two steps per launch on spatial tiles.  A block takes kTwoMG members of a
+// kTwoT x kTwoT tile of nodes: its first step covers the tile and a one-node
+// ring around it (kTwoR x kTwoR nodes, one thread per node and member, exactly
+// the single step's arithmetic on the same inputs) and keeps the results in
+// LDS, rounded as a store and reload would round them; its second step pulls
+// from there for the tile's nodes and writes them.  HBM traffic per two steps
+// is kTwoR^2 / kTwoT^2 reads plus one write of the tile instead of two reads
+// and two writes (0.69x for 6 x 6 tiles).
+constexpr int kTwoMG = 16;
+constexpr int kTwoT = 6;
+constexpr int kTwoR = kTwoT + 2;
+
+__host__ __device__ constexpr int two_step_lds_doubles() { return kTwoR * kTwoR * 9 * kTwoMG; }
+
+template <typename T>
+__global__ __launch_bounds__(kTwoMG * kTwoR * kTwoR) void stream_collide2_kernel(
+    const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
+    int ny, int members, double tau0, double smag, double mu) {
+    extern __shared__ double mid[];  // [kTwoR * kTwoR][9][kTwoMG]
+    const int groups = members / kTwoMG;
+    const int tiles_x = (nx + kTwoT - 1) / kTwoT;
+    const int b = blockIdx.x;
+    const int mg = b % groups, tile = b / groups;
+    const int x0 = (tile % tiles_x) * kTwoT, y0 = (tile / tiles_x) * kTwoT;
+    const int m = mg * kTwoMG + threadIdx.x;
+    const int r = threadIdx.y, rx = r % kTwoR, ry = r / kTwoR;
+    // this thread's region node, periodic (a ragged edge tile computes a few
+    // nodes nobody reads)
+    const int gx = (x0 - 1 + rx + nx) % nx, gy = (y0 - 1 + ry + ny) % ny;
+    const int plane = nx * ny;
+    const int node = gy * nx + gx;
+    double fx = 0.0, fy = 0.0;
+    if (force) {
+        fx = force[node];
+        fy = force[plane + node];
+    }
+    // first step: the single step's pull and collision
+    double f[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        f[a] = PopIO<T>::load_nt(fin + slot(src_node(gx, gy, a, nx, ny), a, m, members), a);
+    collide_node(f, tau0, smag, fx, fy, mu);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) mid[(r * 9 + a) * kTwoMG + threadIdx.x] = PopIO<T>::round(f[a], a);
+    __syncthreads();
+    // second step for the tile's own nodes
+    const int ix = rx - 1, iy = ry - 1;
+    if (ix < 0 || ix >= kTwoT || iy < 0 || iy >= kTwoT || x0 + ix >= nx || y0 + iy >= ny) return;
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        f[a] = mid[(((ry - cy_of(a)) * kTwoR + rx - cx_of(a)) * 9 + a) * kTwoMG + threadIdx.x];
+    collide_node(f, tau0, smag, fx, fy, mu);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
 }
 
 // storage slot (node (x, y), a, m) <- canonical [m][a][y + c_ay][x + c_ax]
@@ -272,6 +333,39 @@ hipError_t launch_stream_collide(const void* fin, void* fout, const double* forc
     else
         stream_collide_kernel<double, 1><<<grid, block, 0, s>>>(
             (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
+    return hipGetLastError();
+}
+
+bool two_step_supported(LbmDims d, int storage) {
+    // FP32 storage keeps one step per launch: its two-members-per-thread step is faster
+    return storage == kStoreF64 && d.members % kTwoMG == 0;
+}
+
+hipError_t launch_stream_collide2(const void* fin, void* fout, const double* force, LbmDims d,
+                                  double tau0, double cs, double mu, int storage, hipStream_t s) {
+    const int tiles = ((d.nx + kTwoT - 1) / kTwoT) * ((d.ny + kTwoT - 1) / kTwoT);
+    const dim3 grid(tiles * (d.members / kTwoMG)), block(kTwoMG, kTwoR * kTwoR);
+    const size_t bytes = (size_t)two_step_lds_doubles() * sizeof(double);
+    const double smag = 18.0 * sqrt(2.0) * cs * cs;
+    static bool attr64 = false, attr32 = false;
+    hipError_t e = hipSuccess;
+    if (storage == kStoreF32Dev) {
+        if (!attr32)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel<float>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr32 = true;
+        stream_collide2_kernel<float><<<grid, block, bytes, s>>>(
+            (const float*)fin, (float*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
+    } else {
+        if (!attr64)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel<double>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr64 = true;
+        stream_collide2_kernel<double><<<grid, block, bytes, s>>>(
+            (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
+    }
     return hipGetLastError();
 }
 
