@@ -140,7 +140,9 @@ lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical,
 
 /* Forecast (Sec. 2 LBE): advance every member nsteps >= 0 steps of
  * fused pull-stream + collide, in place on d_f (storage layout; the
- * workspace holds the ping-pong partner). */
+ * workspace holds the ping-pong partner).  With FP64 storage and 16 | M,
+ * pairs of steps run in one launch (spatial tiles, the intermediate state on
+ * chip); the result is bit-identical to nsteps single-step calls. */
 lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* stream);
 
 /* Observation operator y = H x (Sec. 3): d_yf[M][nvar * n_points]. */
