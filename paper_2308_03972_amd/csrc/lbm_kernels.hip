@@ -29,6 +29,17 @@ constexpr int kBlock = 256;
 __device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 
+// c_a . (x, y) for the D2Q9 velocity a (a constant after unrolling) as the one
+// addition or sign change it needs: a multiplication by 0 or +-1 would cost an
+// instruction and, without fast-math, is not dropped by the compiler.
+__device__ __forceinline__ double cdot(int a, double x, double y) {
+    const int cx = cx_of(a), cy = cy_of(a);
+    const double tx = cx > 0 ? x : (cx < 0 ? -x : 0.0);
+    if (cy == 0) return tx;
+    if (cx == 0) return cy > 0 ? y : -y;
+    return cy > 0 ? tx + y : tx - y;
+}
+
 // Relax one node: f[9] in (pre-collision), f*[9] out.  The multiply-adds are
 // written out as fma() and the compiler may fuse nothing else, so the result
 // does not depend on the code the function is inlined into: the one-step and
@@ -54,10 +65,10 @@ __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double
     const double one_usq = 1.0 - 1.5 * (uu + vv);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const double cu = cx_of(a) * u + cy_of(a) * v;
+        const double cu = cdot(a, u, v);
         // f^eq = rho w (1 + 3 cu + 4.5 cu^2 - 1.5 u.u)
         const double feq = (rho * w_of(a)) * fma(cu, fma(4.5, cu, 3.0), one_usq);
-        const double Fa = (3.0 * w_of(a) * rho) * (cx_of(a) * gx + cy_of(a) * gy);
+        const double Fa = (3.0 * w_of(a) * rho) * cdot(a, gx, gy);
         f[a] = fma(-omega, f[a] - feq, f[a] + Fa);
     }
 }
