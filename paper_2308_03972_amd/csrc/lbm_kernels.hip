@@ -1,6 +1,6 @@
 // Forecast kernels: the D2Q9 lattice Boltzmann equation with BGK relaxation,
 // Smagorinsky eddy viscosity and a body force (Sec. 2), advanced for every
-// ensemble member in one launch.
+// ensemble member in one launch (one step, or two steps on spatial tiles).
 //
 // Layout: f[node][a][member], node = y * nx + x, members fastest (FP64, or
 // FP32 deviations).  One thread per (node, member), a block of
