@@ -323,7 +323,8 @@ lbmletkf_status lbmletkf_batch_destroy(void* batch);
  * fraction of the per-launch cost; its per-launch figure includes the gaps
  * between the back-to-back launches); 0 turns timing off.  Other values:
  * LBMLETKF_EINVAL.  lbmletkf_profile_collect waits for the pairs and returns,
- * per stage, the summed milliseconds and launch counts, then clears the
+ * per stage, the summed milliseconds and launch counts (stage 0 counts
+ * forecast steps: a launch that takes two steps counts 2), then clears the
  * record.  Stages: 0 stream-collide (also the steps of the misfit sweeps),
  * 1 observe, 2 obs statistics, 3 analysis (all node groups of one call),
  * 4 diagnostics, 5 adjoint step, 6 misfit terms. */
