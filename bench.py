@@ -490,9 +490,13 @@ def main() -> int:
     # and its real HBM traffic (PMC) is below them, since the intermediate
     # state stays on chip
     lbm_steps_per_launch = 2 if cfg.members % 16 == 0 else 1
-    # mean local observations per node from the planner's table statistics
-    n_local = cfg.nvar * ectx.max_local_points
-    an_flops = analysis_flops_per_node(ectx.route, cfg.members, n_local, ectx.eig_size) * plane
+    # each node priced at its own local observation count (the planner's
+    # histogram of local points per node)
+    hist = ectx.local_histogram()
+    an_flops = float(sum(int(cnt) * analysis_flops_per_node(ectx.route, cfg.members,
+                                                            cfg.nvar * k, ectx.eig_size)
+                         for k, cnt in enumerate(hist) if cnt))
+    n_local = cfg.nvar * float(np.dot(np.arange(len(hist)), hist)) / max(1, int(hist.sum()))
     an_tflops = an_flops / t_an / 1e12
     lbm_kernel = "stream_collide2_kernel" if lbm_steps_per_launch == 2 else "stream_collide_kernel"
     rec = traffic_record(lbm_kernel) if cfg.name == "paper" else None
@@ -513,6 +517,8 @@ def main() -> int:
              "frac": round(an_tflops / FP64_PEAK_TFLOPS, 4),
              "traffic": an_rec["bytes_per_launch"] if an_rec else None,
              "traffic_note": "HBM bytes of one analysis (all node-group launches)",
+             "algorithmic_flops": round(an_flops),
+             "mean_local_obs": round(n_local, 3),
              "avg_launch_us": round(per_launch["analysis"] * 1e3, 2)}
     dominant = rl_lbm if per_cycle["stream_collide"] >= per_cycle["analysis"] else rl_an
     other = rl_an if dominant is rl_lbm else rl_lbm
