@@ -760,6 +760,29 @@ lbmletkf_status segment_steps(Ctx* c, const Sweep& sw, int t, int steps, int las
     return LBMLETKF_OK;
 }
 
+// The whole segment from checkpoint t - 1 to checkpoint t when its
+// intermediate states are not kept: pairs of steps in one launch where the
+// ensemble allows it (the same bits as single steps), a single step for an
+// odd remainder; states in between pass through the segment buffers.
+lbmletkf_status segment_advance(Ctx* c, const Sweep& sw, int t, int steps, double cs,
+                                hipStream_t s) {
+    const bool two = two_step_supported(c->dims, c->storage());
+    const void* in = sw.ckpt(t - 1);
+    for (int j = 0; j < steps;) {
+        const int n = (two && steps - j >= 2) ? 2 : 1;
+        void* out = j + n == steps ? sw.ckpt_mut(t) : sw.seg(j + n);
+        StageTimer tm(c, kStageCollide, s, kPerLaunch, n);
+        hipError_t e = n == 2 ? launch_stream_collide2(in, out, c->force(), c->dims, c->lbm.tau0,
+                                                       cs, c->lbm.mu, c->storage(), s)
+                              : launch_stream_collide(in, out, c->force(), c->dims, c->lbm.tau0,
+                                                      cs, c->lbm.mu, c->storage(), s);
+        if (e != hipSuccess) return hip_fail(e, "stream_collide");
+        in = out;
+        j += n;
+    }
+    return LBMLETKF_OK;
+}
+
 }  // namespace
 
 lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
@@ -780,7 +803,7 @@ lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
     hipError_t e = launch_fill(jbuf, nj, 0.0, s);
     if (e != hipSuccess) return hip_fail(e, "fill");
     for (int t = 1; t <= n_times; ++t) {
-        if ((st = segment_steps(c, sw, t, steps_per_obs, steps_per_obs, cs, s))) return st;
+        if ((st = segment_advance(c, sw, t, steps_per_obs, cs, s))) return st;
         StageTimer tm(c, kStageMisfit, s);
         e = launch_misfit(sw.ckpt(t), c->pts(), c->obs.n_points, c->obs.nvar,
                           d_yo + (size_t)(t - 1) * c->nobs, nullptr, jbuf, c->dims, c->storage(),
