@@ -97,6 +97,22 @@ def test_misfit_gradient_matches_oracle_fp64(nvar):
     assert np.count_nonzero(gr) > 0.5 * gr.size     # the sensitivity has spread
 
 
+def test_misfit_gradient_two_step_forward_fp64():
+    """16 members in FP64 storage: the forward sweep takes pairs of steps per
+    launch, and s = 5 leaves one single step per interval (the reverse sweep
+    recomputes single steps); 24 x 20 lattice, 3 observation times."""
+    say("adjoint fp64, 16 members, two-step forward")
+    p = _problem(801, 16, 20, 24, npts=6, nvar=2, n_times=3, s=5)
+    J, (g, gcs) = _gpu_gradient(p)
+    Jr, gr, gcsr = _oracle_gradient(p)
+    scale = np.max(np.abs(gr))
+    say(f"J {J:.6e} vs {Jr:.6e}; grad rel {np.max(np.abs(g - gr)) / scale:.2e}; "
+        f"dJ/dCs {gcs:.6e} vs {gcsr:.6e}")
+    assert abs(J - Jr) <= 1e-13 * Jr
+    assert np.max(np.abs(g - gr)) <= 1e-11 * scale
+    assert abs(gcs - gcsr) <= 1e-11 * abs(gcsr)
+
+
 @pytest.mark.parametrize("case", ["one_step", "cs_zero_single_member", "min_grid"])
 def test_misfit_gradient_edge_cases(case):
     say(f"adjoint edge {case}")
