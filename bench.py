@@ -61,7 +61,7 @@ def log(msg: str) -> None:
 
 
 def analysis_flops_per_node(route: int, members: int, n_local: float, n_eig: int) -> float:
-    """Algorithmic FP64 work of one node's analysis.
+    """Algorithmic FP64 work of one node's analysis, textbook operation counts.
 
     Ensemble route: A = aI + Z^T Z (l M^2), the M x M symmetric
     eigendecomposition with vectors counted at the textbook 9 M^3, the
