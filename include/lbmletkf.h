@@ -65,7 +65,7 @@ typedef enum {
     LBMLETKF_EDIVERGED = -5,   /* spread or RMSE above the divergence limit */
     LBMLETKF_EEIG = -6,        /* eigensolver did not converge */
     LBMLETKF_EWORKSPACE = -7,  /* workspace missing, misaligned or too small */
-    LBMLETKF_EUNSUPPORTED = -8 /* valid request this build does not implement */
+    LBMLETKF_EUNSUPPORTED = -8 /* a valid request the library does not implement */
 } lbmletkf_status;
 
 /* Storage of the populations in every state buffer d_f:
