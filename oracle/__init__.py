@@ -25,7 +25,9 @@ Contents and the passage each follows:
   dW = [(M-1) P~a]^(1/2) (symmetric square root),
   x_m^a = x_bar + dX (w_bar + dW[:, m]).
 * ``rmse`` -- RMSE of the ensemble-mean velocity (Sec. 4.3.1).
-* ``energy_spectrum`` -- shell-summed energy spectrum (Sec. 4.1).
+* ``energy_spectrum`` -- shell-summed energy spectrum (Sec. 4.1);
+  ``member_mean_spectrum`` -- the ensemble's spectrum as the mean of the
+  members' spectra (Sec. 4.3.2).
 * ``run_cycles`` -- the workflow of Sec. 3: forecast s steps, observe the
   truth, analyse, repeat.
 * ``oracle.adjoint`` (submodule) -- the gradient of the observation misfit
@@ -304,37 +306,62 @@ def energy_spectrum(u, v) -> np.ndarray:
     return np.bincount(shell.ravel(), weights=e.ravel())
 
 
+def member_mean_spectrum(f) -> np.ndarray:
+    """Ensemble spectrum M^-1 sum_m E_m(k), E_m the spectrum of member m's
+    velocity (the mean of the members' spectra, Sec. 4.3.2); f [M][9][n][n]."""
+    mo = moments(f)
+    specs = [energy_spectrum(mo[1, m], mo[2, m]) for m in range(mo.shape[1])]
+    return np.mean(np.stack(specs), axis=0)
+
+
 # ---------------------------------------------------------------------------
 # forecast-analysis cycle (Sec. 3 workflow, Sec. 4.3 OSSE)
 # ---------------------------------------------------------------------------
 def run_cycles(f_ens, f_truth, params, force, points, noise, cycles: Optional[int] = None,
-               keep_states: bool = False) -> Dict[str, object]:
-    """Run ``cycles`` forecast-analysis cycles.
+               keep_states: bool = False, analyze=None,
+               report_every: int = 0) -> Dict[str, object]:
+    """Run ``cycles`` forecast-analysis cycles (Sec. 3 workflow (ii)-(v)).
 
     params: any object with n, tau0, cs, mu, steps_per_cycle, nvar, sigmas,
     d_cut, beta.  noise: [cycles][n_obs] standard normals; observation
-    q of cycle c is y^o = H(truth) + sigma_q * noise[c-1][q].
+    q of cycle c is y^o = H(truth) + sigma_q * noise[c-1][q], taken from the
+    truth after it has been advanced to the analysis time c * s.  RMSE_f and
+    spread_f are those of the forecast (before the analysis), RMSE_a and
+    spread_a those of the analysis.  ``analyze``: the analysis function
+    (default ``letkf_analysis``; any callable with its signature and result,
+    e.g. the same function mapped over node subsets).  With report_every = k
+    > 0 the member-mean spectrum of the analysis ensemble and the truth's
+    spectrum are recorded at every k-th cycle.
     """
     cycles = len(noise) if cycles is None else cycles
+    analyze = letkf_analysis if analyze is None else analyze
     sig = np.tile(np.asarray(params.sigmas, dtype=np.float64), len(points))
     f_ens = np.array(f_ens, dtype=np.float64)
     f_truth = np.array(f_truth, dtype=np.float64)
-    hist = {"rmse_f": [], "rmse_a": [], "spread_f": [], "spread_a": [], "yo": []}
+    hist = {"rmse_f": [], "rmse_a": [], "spread_f": [], "spread_a": [], "yo": [],
+            "report_cycle": [], "spectrum_a": [], "spectrum_t": []}
     states = []
     for c in range(1, cycles + 1):
+        # (ii) forecast: truth and members advance s steps
         f_truth = lbm_steps(f_truth, params.steps_per_cycle, params.tau0, params.cs, force,
                             params.mu)
         f_ens = lbm_steps(f_ens, params.steps_per_cycle, params.tau0, params.cs, force,
                           params.mu)
+        # (iii) observe the truth at the analysis time
         yo = observe(f_truth, points, params.nvar)[0] + sig * np.asarray(noise[c - 1])
         yf = observe(f_ens, points, params.nvar)
         hist["rmse_f"].append(rmse(f_ens, f_truth))
         hist["spread_f"].append(spread(f_ens))
-        f_ens = letkf_analysis(f_ens, yf, yo, points, params.sigmas, params.d_cut,
-                               params.beta)
+        # (iv) analysis
+        f_ens = analyze(f_ens, yf, yo, points, params.sigmas, params.d_cut, params.beta)
         hist["rmse_a"].append(rmse(f_ens, f_truth))
         hist["spread_a"].append(spread(f_ens))
         hist["yo"].append(yo)
+        if report_every > 0 and c % report_every == 0:
+            mt = moments(f_truth)
+            hist["report_cycle"].append(c)
+            hist["spectrum_a"].append(member_mean_spectrum(f_ens))
+            hist["spectrum_t"].append(energy_spectrum(mt[1, 0], mt[2, 0]))
         if keep_states:
             states.append(f_ens.copy())
     out = {k: np.asarray(v) for k, v in hist.items()}
