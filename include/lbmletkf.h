@@ -113,6 +113,12 @@ typedef struct {
     int32_t route;           /* lbmletkf_route */
 } lbmletkf_obs_params;
 
+/* Opaque host-side handles: a context (one ensemble with its observing
+ * network, holding parameters and pointers into the caller's workspace) and a
+ * batch of contexts (batching form). */
+typedef struct lbmletkf_ctx lbmletkf_ctx;
+typedef struct lbmletkf_batch lbmletkf_batch;
+
 /* Size of the device workspace a context needs (bytes, 256-byte aligned base). */
 lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
                                          const lbmletkf_obs_params* obs, size_t* bytes);
@@ -124,36 +130,36 @@ lbmletkf_status lbmletkf_workspace_bytes(const lbmletkf_lbm_params* lbm,
  * (observations with Gaspari-Cohn weight > 0) and waits for it. */
 lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
                                 const double* d_force, void* d_workspace, size_t bytes,
-                                void* stream, void** ctx_out);
+                                void* stream, lbmletkf_ctx** ctx_out);
 
 /* Free the host context (the workspace stays with the caller). */
-lbmletkf_status lbmletkf_destroy(void* ctx);
+lbmletkf_status lbmletkf_destroy(lbmletkf_ctx* ctx);
 
 /* Equilibrium state f^eq(rho, u) (Sec. 2 equilibrium) in storage layout.
  * d_rho: [M][ny][nx] or NULL for rho = 1; d_uv: [M][2][ny][nx]. */
-lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const double* d_uv,
+lbmletkf_status lbmletkf_init_equilibrium(lbmletkf_ctx* ctx, const double* d_rho, const double* d_uv,
                                           void* d_f, void* stream);
 
 /* canonical -> storage and storage -> canonical (buffers must not overlap). */
-lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, void* d_f, void* stream);
-lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical, void* stream);
+lbmletkf_status lbmletkf_import(lbmletkf_ctx* ctx, const double* d_canonical, void* d_f, void* stream);
+lbmletkf_status lbmletkf_export(lbmletkf_ctx* ctx, const void* d_f, double* d_canonical, void* stream);
 
 /* Forecast (Sec. 2 LBE): advance every member nsteps >= 0 steps of
  * fused pull-stream + collide, in place on d_f (storage layout; the
  * workspace holds the ping-pong partner).  With FP64 storage and 16 | M,
  * pairs of steps run in one launch (spatial tiles, the intermediate state on
  * chip); the result is bit-identical to nsteps single-step calls. */
-lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* stream);
+lbmletkf_status lbm_ensemble_step(lbmletkf_ctx* ctx, void* d_f, int32_t nsteps, void* stream);
 
 /* Observation operator y = H x (Sec. 3): d_yf[M][nvar * n_points]. */
-lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream);
+lbmletkf_status observe(lbmletkf_ctx* ctx, const void* d_f, double* d_yf, void* stream);
 
 /* LETKF analysis (Sec. 3.2.1, Sec. 3.2.2), in place on d_f:
  * ensemble statistics of d_yf against d_yo[nvar * n_points], then at every
  * node the localized ensemble-space problem, its symmetric
  * eigendecomposition, w_bar, dW = [(M-1) P~a]^(1/2) and
  * x_m^a = x_bar + dX (w_bar + dW[:, m]) applied to the nine populations. */
-lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
+lbmletkf_status letkf_analyze(lbmletkf_ctx* ctx, void* d_f, const double* d_yf, const double* d_yo,
                               void* stream);
 
 /* Ensemble diagnostics into d_diag[LBMLETKF_DIAG_LEN]: RMSE of the
@@ -165,7 +171,7 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
 #define LBMLETKF_DIAG_NONFINITE 2
 #define LBMLETKF_DIAG_RHO_MIN 3
 #define LBMLETKF_DIAG_RHO_MAX 4
-lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d_truth_uv,
+lbmletkf_status lbmletkf_diagnostics(lbmletkf_ctx* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream);
 
 /* One forecast-analysis cycle (Sec. 3 workflow (ii)-(iv)):
@@ -177,12 +183,54 @@ lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d
  * forecast and analysis (no extra pass over the state) and summed over the
  * nodes in a fixed order of their own, so they agree with separate
  * lbmletkf_diagnostics calls to rounding.  The ensemble must have >= 2
- * members (LBMLETKF_EINVAL before any launch otherwise). */
-lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_yo,
+ * members (LBMLETKF_EINVAL before any launch otherwise).  With
+ * check_every_cycle set (lbmletkf_set_checks) and d_diag != NULL, run_cycle
+ * waits for the cycle and returns the status of lbmletkf_check. */
+lbmletkf_status run_cycle(lbmletkf_ctx* ctx, void* d_f, int32_t nsteps, const double* d_yo,
                           const double* d_truth_uv, double* d_diag, void* stream);
 
+/* ---- health checks (failure detection) -------------------------------------
+ *
+ * The failure mode the paper reports is catastrophic filter divergence
+ * (Sec. 4.3.3); numerically an ensemble can also turn non-finite, and a node's
+ * Jacobi eigensolver can stop at its sweep cap without converging.
+ *   max_sweeps         cap of the analysis eigensolvers' Jacobi sweeps, 1..100
+ *                      (default 30; converged solves take 4-8); a node that
+ *                      reaches it is counted and its weights are used as they are;
+ *   diverge_limit      run_cycle's divergence threshold on the analysis RMSE and
+ *                      spread (same units as the velocity; <= 0 or inf: none,
+ *                      the default);
+ *   check_every_cycle  1: run_cycle with d_diag != NULL waits for its
+ *                      diagnostics and returns the health status below (one
+ *                      stream synchronisation per cycle); 0 (default): no wait,
+ *                      call lbmletkf_check when convenient.
+ * The batching form takes max_sweeps from each context at lbmletkf_batch_create. */
+lbmletkf_status lbmletkf_set_checks(lbmletkf_ctx* ctx, int32_t max_sweeps, double diverge_limit,
+                                    int32_t check_every_cycle);
+
+/* Waits for `stream`, then returns the health of the analyses since the last
+ * check, in this order: LBMLETKF_ENONFINITE if d_diag (NULL, or a run_cycle
+ * diagnostics record of 16 doubles) counts members with a non-finite density
+ * or velocity or holds a non-finite RMSE/spread; LBMLETKF_EEIG if any node's
+ * eigensolver reached the sweep cap; LBMLETKF_EDIVERGED if the record's
+ * analysis RMSE or spread exceeds the divergence limit; else LBMLETKF_OK.  The
+ * counts are in lbmletkf_last_error().  Clears the sweep-cap counter. */
+lbmletkf_status lbmletkf_check(lbmletkf_ctx* ctx, const double* d_diag, void* stream);
+
+/* Energy spectrum of the ensemble at a report time (Sec. 4.1 shell spectrum;
+ * the ensemble's spectrum is the mean of the members' spectra, Sec. 4.3.2):
+ * d_E[k] (device, kmax + 1 doubles) for k = 0 .. kmax (0 <= kmax <= n) =
+ * M^-1 sum_m sum over the integer wavevectors k' with k - 1/2 <= |k'| < k + 1/2
+ * of (|u_hat_m(k')|^2 + |v_hat_m(k')|^2) / 2, u_hat = n^-2 sum_xi u e^{-i k'.xi}
+ * (xi in cells, k' in units of 2 pi / n), u = j / rho of member m.  Square
+ * grids n <= 2048 only (LBMLETKF_ESHAPE otherwise).  Uses the workspace's
+ * ping-pong buffer as scratch (free between calls).  Direct DFT sums in FP64,
+ * deterministic; not for the hot loop (about 1 ms at 256^2 x 64 members). */
+lbmletkf_status lbmletkf_energy_spectrum(lbmletkf_ctx* ctx, const void* d_f, double* d_E, int32_t kmax,
+                                         void* stream);
+
 /* rho, u, v of every node of every member: d_out[M][3][ny][nx]. */
-lbmletkf_status lbmletkf_moments(void* ctx, const void* d_f, double* d_out, void* stream);
+lbmletkf_status lbmletkf_moments(lbmletkf_ctx* ctx, const void* d_f, double* d_out, void* stream);
 
 /* Synthetic observations y^o_q = y_q + sigma_q * eps_q for q < n (OSSE,
  * Sec. 4.3); all three arrays and d_yo are device [n]. */
@@ -197,12 +245,12 @@ lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs
 
 /* Introspection: local-observation points per node (max over nodes), the
  * eigenproblem size the analysis uses and its route (after AUTO). */
-lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig_size,
+lbmletkf_status lbmletkf_info(lbmletkf_ctx* ctx, int32_t* max_local_points, int32_t* eig_size,
                               int32_t* route);
 
 /* Host-only: hist[k] = number of nodes with exactly k observation points in
  * their localization support, for k < len (larger counts are not reported). */
-lbmletkf_status lbmletkf_local_histogram(void* ctx, int32_t* hist, int32_t len);
+lbmletkf_status lbmletkf_local_histogram(lbmletkf_ctx* ctx, int32_t* hist, int32_t len);
 
 /* ---- differentiation form: reverse mode of the Sec. 2 forecast -----------
  *
@@ -233,7 +281,7 @@ lbmletkf_status lbmletkf_adjoint_workspace_bytes(const lbmletkf_lbm_params* lbm,
 
 /* Forward sweep: J into d_J[0] (device) and the checkpoints into d_work.
  * d_f0 is not modified.  steps_per_obs >= 1, n_times >= 1, cs >= 0. */
-lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
+lbmletkf_status lbmletkf_misfit_forward(lbmletkf_ctx* ctx, const void* d_f0, double cs,
                                         int32_t steps_per_obs, int32_t n_times,
                                         const double* d_yo, double* d_J, void* d_work,
                                         size_t work_bytes, void* stream);
@@ -247,7 +295,7 @@ lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
  * rounding of the stored deviations counts as the identity).  d_grad_f0 must
  * not overlap d_f0, d_yo or the workspace.  The observation points must be
  * distinct (LBMLETKF_EUNSUPPORTED otherwise). */
-lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
+lbmletkf_status lbmletkf_misfit_backward(lbmletkf_ctx* ctx, const void* d_f0, double cs,
                                          int32_t steps_per_obs, int32_t n_times,
                                          const double* d_yo, void* d_work, size_t work_bytes,
                                          double* d_grad_f0, double* d_grad_cs, void* stream);
@@ -282,26 +330,26 @@ typedef struct {
     int32_t use_graph;          /* 1: capture the cycle once as a hipGraph and replay it */
 } lbmletkf_batch_config;
 
-lbmletkf_status lbmletkf_batch_workspace_bytes(void* const* ctxs, int32_t n, size_t* bytes);
+lbmletkf_status lbmletkf_batch_workspace_bytes(lbmletkf_ctx* const* ctxs, int32_t n, size_t* bytes);
 
 /* Create a batch of n contexts with states d_f[k] (device, storage layout) and
  * nsteps forecast steps per cycle.  ctxs and d_f are host arrays of n pointers.
  * cfg may be NULL: {one block per tile, 4 tile rows, granularity 2, graph}.  Waits for
  * its setup copies and, with use_graph, captures the cycle. */
-lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32_t n,
+lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_f, int32_t n,
                                       int32_t nsteps, const lbmletkf_batch_config* cfg,
                                       void* d_workspace, size_t bytes, void* stream,
-                                      void** batch_out);
+                                      lbmletkf_batch** batch_out);
 
 /* One cycle of every problem.  d_yo: host array of n device pointers, d_yo[k]
  * = this cycle's observations of problem k ([nvar * n_points], copied in on
  * `stream` before the cycle). */
-lbmletkf_status lbmletkf_batch_run_cycle(void* batch, const double* const* d_yo, void* stream);
+lbmletkf_status lbmletkf_batch_run_cycle(lbmletkf_batch* batch, const double* const* d_yo, void* stream);
 
-lbmletkf_status lbmletkf_batch_get_config(void* batch, lbmletkf_batch_config* cfg);
+lbmletkf_status lbmletkf_batch_get_config(lbmletkf_batch* batch, lbmletkf_batch_config* cfg);
 
 /* Re-tile, re-group and (with use_graph) re-capture; waits for its setup. */
-lbmletkf_status lbmletkf_batch_set_config(void* batch, const lbmletkf_batch_config* cfg,
+lbmletkf_status lbmletkf_batch_set_config(lbmletkf_batch* batch, const lbmletkf_batch_config* cfg,
                                           void* stream);
 
 /* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048, 0}) x
@@ -310,10 +358,10 @@ lbmletkf_status lbmletkf_batch_set_config(void* batch, const lbmletkf_batch_conf
  * the fastest with use_graph = 1.  Runs on the contexts' ping-pong partner
  * buffers: the bound states are not modified.  Outputs (any may be NULL): the
  * chosen configuration, its forecast ms per step and analysis ms per cycle. */
-lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_config* best,
+lbmletkf_status lbmletkf_batch_tune(lbmletkf_batch* batch, int32_t reps, lbmletkf_batch_config* best,
                                     double* forecast_ms, double* analysis_ms, void* stream);
 
-lbmletkf_status lbmletkf_batch_destroy(void* batch);
+lbmletkf_status lbmletkf_batch_destroy(lbmletkf_batch* batch);
 
 /* Per-stage GPU timing with HIP events on the launch stream.  enable = 1:
  * every launch is bracketed by an event pair; enable = 2: one pair around the
@@ -329,8 +377,8 @@ lbmletkf_status lbmletkf_batch_destroy(void* batch);
  * 1 observe, 2 obs statistics, 3 analysis (all node groups of one call),
  * 4 diagnostics, 5 adjoint step, 6 misfit terms. */
 #define LBMLETKF_NSTAGES 7
-lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable);
-lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts);
+lbmletkf_status lbmletkf_set_profiling(lbmletkf_ctx* ctx, int32_t enable);
+lbmletkf_status lbmletkf_profile_collect(lbmletkf_ctx* ctx, double* ms, int64_t* counts);
 
 const char* lbmletkf_status_string(int32_t status);
 const char* lbmletkf_last_error(void);

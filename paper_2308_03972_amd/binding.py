@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmletkf.so")
 
 LBMLETKF_OK = 0
+LBMLETKF_ENONFINITE, LBMLETKF_EDIVERGED, LBMLETKF_EEIG = -4, -5, -6
 DIAG_LEN = 8
 NSTAGES = 7
 STAGES = ("stream_collide", "observe", "obs_stats", "analysis", "diagnostics", "adjoint",
@@ -73,6 +74,9 @@ SIGNATURES = {
     "lbmletkf_diagnostics": (_c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "run_cycle": (_c_int32, [_vp, _vp, _c_int32, _vp, _vp, _vp, _vp]),
     "lbmletkf_moments": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "lbmletkf_set_checks": (_c_int32, [_vp, _c_int32, _c_double, _c_int32]),
+    "lbmletkf_check": (_c_int32, [_vp, _vp, _vp]),
+    "lbmletkf_energy_spectrum": (_c_int32, [_vp, _vp, _vp, _c_int32, _vp]),
     "lbmletkf_synth_obs": (_c_int32, [_vp, _vp, _vp, _vp, _c_int32, _vp]),
     "lbmletkf_plan": (_c_int32, [ctypes.POINTER(LbmParams), ctypes.POINTER(ObsParams),
                                  ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32),
@@ -431,6 +435,26 @@ class Context:
                           device=self.device)
         _check(load().lbmletkf_moments(self.handle, self._state(f), _dev(out), _stream(stream)))
         return out
+
+    def energy_spectrum(self, f: torch.Tensor, kmax: Optional[int] = None,
+                        stream=None) -> torch.Tensor:
+        """Member-mean shell energy spectrum E[0..kmax] (default kmax = n // 2)."""
+        kmax = self.nx // 2 if kmax is None else int(kmax)
+        out = torch.empty(kmax + 1, dtype=torch.float64, device=self.device)
+        _check(load().lbmletkf_energy_spectrum(self.handle, self._state(f), _dev(out), kmax,
+                                               _stream(stream)))
+        return out
+
+    # -- health checks -------------------------------------------------------------
+    def set_checks(self, max_sweeps: int = 30, diverge_limit: float = 0.0,
+                   check_every_cycle: bool = False) -> None:
+        _check(load().lbmletkf_set_checks(self.handle, int(max_sweeps), float(diverge_limit),
+                                          int(bool(check_every_cycle))))
+
+    def check(self, diag: Optional[torch.Tensor] = None, stream=None) -> None:
+        """Raises LbmLetkfError (status ENONFINITE, EEIG or EDIVERGED) if unhealthy."""
+        _check(load().lbmletkf_check(self.handle, _dev(diag, 2 * DIAG_LEN, "diag"),
+                                     _stream(stream)))
 
     def local_histogram(self) -> np.ndarray:
         """Nodes per number of local observation points (index = count)."""

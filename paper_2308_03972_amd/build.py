@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmletkf.so")
-SOURCES = ["api.hip", "lbm_kernels.hip", "letkf_kernels.hip", "letkf_obs.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "lbm_kernels.hip", "letkf_kernels.hip", "letkf_obs.hip", "adjoint.hip",
+           "spectrum.hip"]
 ARCH = os.environ.get("LBMLETKF_ARCH", "gfx950")
 
 

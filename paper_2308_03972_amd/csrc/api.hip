@@ -63,6 +63,11 @@ struct Ctx {
     std::vector<int> hist;  // nodes per local-point count
     bool has_force;
     bool distinct_points = true;  // no two observation points on one node
+    // health checks (lbmletkf_set_checks): Jacobi sweep cap, divergence limit on
+    // the analysis spread and RMSE (<= 0: none), check inside every run_cycle
+    int max_sweeps = 30;
+    double diverge_limit = 0.0;
+    bool check_every_cycle = false;
     char* ws;
     Layout L;
     // arguments of the last misfit forward sweep (its checkpoints feed the
@@ -336,7 +341,10 @@ AdjLayout make_adj_layout(const lbmletkf_lbm_params* p, int n_points, int steps,
     return L;
 }
 
-Ctx* as_ctx(void* c) { return reinterpret_cast<Ctx*>(c); }
+// The public handles are opaque: lbmletkf_ctx / lbmletkf_batch are never
+// defined, their pointers carry the internal objects.
+Ctx* as_ctx(lbmletkf_ctx* c) { return reinterpret_cast<Ctx*>(c); }
+lbmletkf_ctx* as_handle(Ctx* c) { return reinterpret_cast<lbmletkf_ctx*>(c); }
 
 void release_streams(Ctx* c) {
     for (int k = 0; k < Ctx::kSide; ++k) {
@@ -370,10 +378,50 @@ AnalysisParams make_params(const Ctx* c, void* d_f) {
         p.rinv[v] = v < c->obs.nvar ? 1.0 / (c->obs.sigma[v] * c->obs.sigma[v]) : 0.0;
     p.a = (c->dims.members - 1) / c->obs.beta;
     p.sqrt_beta = std::sqrt(c->obs.beta);
+    p.max_sweeps = c->max_sweeps;
     p.eig_fail = c->counters() + 1;
     p.truth_uv = nullptr;
     p.diag_node = nullptr;
     return p;
+}
+
+// Waits for the stream, then the health of the analyses since the last check:
+// non-finite members in the diagnostics record (16 doubles, forecast then
+// analysis; may be NULL), nodes whose eigensolver reached the sweep cap (the
+// counter is cleared), the analysis spread or RMSE above the divergence limit.
+lbmletkf_status health_check(Ctx* c, const double* d_diag, hipStream_t s) {
+    int cnt[2] = {0, 0};
+    double dg[16] = {0.0};
+    hipError_t e = hipMemcpyAsync(cnt, c->counters(), sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && d_diag)
+        e = hipMemcpyAsync(dg, d_diag, sizeof(dg), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->counters() + 1, 0, sizeof(int), s);
+    if (e != hipSuccess) return hip_fail(e, "health check");
+    const double nonfinite = dg[2] + dg[8 + 2];
+    const int eig = cnt[1];
+    char msg[256];
+    if (nonfinite > 0.0 || (d_diag && (!std::isfinite(dg[8]) || !std::isfinite(dg[9])))) {
+        std::snprintf(msg, sizeof msg,
+                      "non-finite ensemble: %.0f forecast and %.0f analysis member-nodes with a "
+                      "non-finite density or velocity; %d node eigensolves at the sweep cap",
+                      dg[2], dg[8 + 2], eig);
+        return fail(LBMLETKF_ENONFINITE, msg);
+    }
+    if (eig > 0) {
+        std::snprintf(msg, sizeof msg,
+                      "%d node eigensolves did not converge within %d Jacobi sweeps", eig,
+                      c->max_sweeps);
+        return fail(LBMLETKF_EEIG, msg);
+    }
+    if (d_diag && c->diverge_limit > 0.0 &&
+        (dg[8] > c->diverge_limit || dg[9] > c->diverge_limit)) {
+        std::snprintf(msg, sizeof msg,
+                      "analysis RMSE %.6g or spread %.6g above the divergence limit %.6g", dg[8],
+                      dg[9], c->diverge_limit);
+        return fail(LBMLETKF_EDIVERGED, msg);
+    }
+    return LBMLETKF_OK;
 }
 
 }  // namespace
@@ -428,7 +476,7 @@ lbmletkf_status lbmletkf_plan(const lbmletkf_lbm_params* lbm, const lbmletkf_obs
 
 lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_obs_params* obs,
                                 const double* d_force, void* d_workspace, size_t bytes,
-                                void* stream, void** ctx_out) {
+                                void* stream, lbmletkf_ctx** ctx_out) {
     lbmletkf_status st = check_lbm(lbm);
     if (st) return st;
     if ((st = check_obs(obs, lbm))) return st;
@@ -535,11 +583,11 @@ lbmletkf_status lbmletkf_create(const lbmletkf_lbm_params* lbm, const lbmletkf_o
         delete c;
         return fail(LBMLETKF_EINVAL, "local-observation table overflow");
     }
-    *ctx_out = c;
+    *ctx_out = as_handle(c);
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_destroy(void* ctx) {
+lbmletkf_status lbmletkf_destroy(lbmletkf_ctx* ctx) {
     Ctx* c = as_ctx(ctx);
     if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
     for (auto& r : c->recs) {
@@ -552,7 +600,7 @@ lbmletkf_status lbmletkf_destroy(void* ctx) {
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const double* d_uv,
+lbmletkf_status lbmletkf_init_equilibrium(lbmletkf_ctx* ctx, const double* d_rho, const double* d_uv,
                                           void* d_f, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_uv || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
@@ -560,7 +608,7 @@ lbmletkf_status lbmletkf_init_equilibrium(void* ctx, const double* d_rho, const 
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "init_equilibrium");
 }
 
-lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, void* d_f, void* stream) {
+lbmletkf_status lbmletkf_import(lbmletkf_ctx* ctx, const double* d_canonical, void* d_f, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_canonical || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
     if ((const void*)d_canonical == (const void*)d_f)
@@ -569,7 +617,7 @@ lbmletkf_status lbmletkf_import(void* ctx, const double* d_canonical, void* d_f,
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "import");
 }
 
-lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical, void* stream) {
+lbmletkf_status lbmletkf_export(lbmletkf_ctx* ctx, const void* d_f, double* d_canonical, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_canonical || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
     if ((const void*)d_canonical == (const void*)d_f)
@@ -578,7 +626,7 @@ lbmletkf_status lbmletkf_export(void* ctx, const void* d_f, double* d_canonical,
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "export");
 }
 
-lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* stream) {
+lbmletkf_status lbm_ensemble_step(lbmletkf_ctx* ctx, void* d_f, int32_t nsteps, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f) return fail(LBMLETKF_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(LBMLETKF_EINVAL, "nsteps must be >= 0");
@@ -607,7 +655,7 @@ lbmletkf_status lbm_ensemble_step(void* ctx, void* d_f, int32_t nsteps, void* st
     return LBMLETKF_OK;
 }
 
-lbmletkf_status observe(void* ctx, const void* d_f, double* d_yf, void* stream) {
+lbmletkf_status observe(lbmletkf_ctx* ctx, const void* d_f, double* d_yf, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yf) return fail(LBMLETKF_EINVAL, "NULL argument");
     StageTimer t(c, kStageObserve, as_stream(stream));
@@ -666,7 +714,7 @@ lbmletkf_status analyze_impl(Ctx* c, void* d_f, const double* d_yf, const double
 
 extern "C" {
 
-lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const double* d_yo,
+lbmletkf_status letkf_analyze(lbmletkf_ctx* ctx, void* d_f, const double* d_yf, const double* d_yo,
                               void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yf || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
@@ -674,7 +722,7 @@ lbmletkf_status letkf_analyze(void* ctx, void* d_f, const double* d_yf, const do
     return analyze_impl(c, d_f, d_yf, d_yo, nullptr, nullptr, as_stream(stream));
 }
 
-lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d_truth_uv,
+lbmletkf_status lbmletkf_diagnostics(lbmletkf_ctx* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_diag) return fail(LBMLETKF_EINVAL, "NULL argument");
@@ -685,7 +733,7 @@ lbmletkf_status lbmletkf_diagnostics(void* ctx, const void* d_f, const double* d
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
 }
 
-lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_yo,
+lbmletkf_status run_cycle(lbmletkf_ctx* ctx, void* d_f, int32_t nsteps, const double* d_yo,
                           const double* d_truth_uv, double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
@@ -698,10 +746,50 @@ lbmletkf_status run_cycle(void* ctx, void* d_f, int32_t nsteps, const double* d_
     // diagnostics of the forecast and of the analysis from the analysis kernels'
     // per-node records (they hold each node's forecast and analysis anyway)
     if ((st = analyze_impl(c, d_f, c->yf(), d_yo, d_truth_uv, c->diag_node(), s))) return st;
-    StageTimer t(c, kStageDiag, s);
-    hipError_t e = launch_diag_nodes_final(c->diag_node(), c->dims.nx * c->dims.ny, c->diag_fold(),
-                                           d_diag, d_diag + LBMLETKF_DIAG_LEN, s);
-    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
+    {
+        StageTimer t(c, kStageDiag, s);
+        hipError_t e = launch_diag_nodes_final(c->diag_node(), c->dims.nx * c->dims.ny,
+                                               c->diag_fold(), d_diag, d_diag + LBMLETKF_DIAG_LEN, s);
+        if (e != hipSuccess) return hip_fail(e, "diagnostics");
+    }
+    return c->check_every_cycle ? health_check(c, d_diag, s) : LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_set_checks(lbmletkf_ctx* ctx, int32_t max_sweeps, double diverge_limit,
+                                    int32_t check_every_cycle) {
+    Ctx* c = as_ctx(ctx);
+    if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
+    if (max_sweeps < 1 || max_sweeps > 100) return fail(LBMLETKF_EINVAL, "max_sweeps must be in 1..100");
+    if (std::isnan(diverge_limit)) return fail(LBMLETKF_EINVAL, "diverge_limit is NaN");
+    if (check_every_cycle != 0 && check_every_cycle != 1)
+        return fail(LBMLETKF_EINVAL, "check_every_cycle must be 0 or 1");
+    c->max_sweeps = max_sweeps;
+    c->diverge_limit = (diverge_limit > 0.0 && std::isfinite(diverge_limit)) ? diverge_limit : 0.0;
+    c->check_every_cycle = check_every_cycle != 0;
+    return LBMLETKF_OK;
+}
+
+lbmletkf_status lbmletkf_check(lbmletkf_ctx* ctx, const double* d_diag, void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
+    return health_check(c, d_diag, as_stream(stream));
+}
+
+lbmletkf_status lbmletkf_energy_spectrum(lbmletkf_ctx* ctx, const void* d_f, double* d_E, int32_t kmax,
+                                         void* stream) {
+    Ctx* c = as_ctx(ctx);
+    if (!c || !d_f || !d_E) return fail(LBMLETKF_EINVAL, "NULL argument");
+    const int n = c->dims.nx;
+    if (c->dims.ny != n) return fail(LBMLETKF_ESHAPE, "the spectrum needs a square grid");
+    if (n > 2048) return fail(LBMLETKF_ESHAPE, "the spectrum supports n <= 2048");
+    if (kmax < 0 || kmax > n) return fail(LBMLETKF_EINVAL, "kmax must be in 0..n");
+    if (spectrum_scratch_bytes(n, c->dims.members) > c->state_bytes())
+        return fail(LBMLETKF_EWORKSPACE, "spectrum scratch exceeds the ping-pong buffer");
+    if (d_f == c->fbuf()) return fail(LBMLETKF_EINVAL, "d_f is the workspace's own buffer");
+    StageTimer t(c, kStageDiag, as_stream(stream));
+    hipError_t e = launch_energy_spectrum(d_f, n, c->dims.members, c->storage(), kmax, c->fbuf(),
+                                          d_E, as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "energy_spectrum");
 }
 
 lbmletkf_status lbmletkf_adjoint_workspace_bytes(const lbmletkf_lbm_params* lbm,
@@ -785,7 +873,7 @@ lbmletkf_status segment_advance(Ctx* c, const Sweep& sw, int t, int steps, doubl
 
 }  // namespace
 
-lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
+lbmletkf_status lbmletkf_misfit_forward(lbmletkf_ctx* ctx, const void* d_f0, double cs,
                                         int32_t steps_per_obs, int32_t n_times,
                                         const double* d_yo, double* d_J, void* d_work,
                                         size_t work_bytes, void* stream) {
@@ -816,7 +904,7 @@ lbmletkf_status lbmletkf_misfit_forward(void* ctx, const void* d_f0, double cs,
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
+lbmletkf_status lbmletkf_misfit_backward(lbmletkf_ctx* ctx, const void* d_f0, double cs,
                                          int32_t steps_per_obs, int32_t n_times,
                                          const double* d_yo, void* d_work, size_t work_bytes,
                                          double* d_grad_f0, double* d_grad_cs, void* stream) {
@@ -881,7 +969,7 @@ lbmletkf_status lbmletkf_misfit_backward(void* ctx, const void* d_f0, double cs,
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_moments(void* ctx, const void* d_f, double* d_out, void* stream) {
+lbmletkf_status lbmletkf_moments(lbmletkf_ctx* ctx, const void* d_f, double* d_out, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c || !d_f || !d_out) return fail(LBMLETKF_EINVAL, "NULL argument");
     hipError_t e = launch_moments(d_f, d_out, c->dims, c->storage(), as_stream(stream));
@@ -897,7 +985,7 @@ lbmletkf_status lbmletkf_synth_obs(const double* d_y, const double* d_eps, const
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "synth_obs");
 }
 
-lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig_size,
+lbmletkf_status lbmletkf_info(lbmletkf_ctx* ctx, int32_t* max_local_points, int32_t* eig_size,
                               int32_t* route) {
     Ctx* c = as_ctx(ctx);
     if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
@@ -907,14 +995,14 @@ lbmletkf_status lbmletkf_info(void* ctx, int32_t* max_local_points, int32_t* eig
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_local_histogram(void* ctx, int32_t* hist, int32_t len) {
+lbmletkf_status lbmletkf_local_histogram(lbmletkf_ctx* ctx, int32_t* hist, int32_t len) {
     Ctx* c = as_ctx(ctx);
     if (!c || !hist || len < 0) return fail(LBMLETKF_EINVAL, "bad argument");
     for (int k = 0; k < len; ++k) hist[k] = k < (int)c->hist.size() ? c->hist[k] : 0;
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable) {
+lbmletkf_status lbmletkf_set_profiling(lbmletkf_ctx* ctx, int32_t enable) {
     Ctx* c = as_ctx(ctx);
     if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
     if (enable < 0 || enable > 2) return fail(LBMLETKF_EINVAL, "profiling level must be 0, 1 or 2");
@@ -922,7 +1010,7 @@ lbmletkf_status lbmletkf_set_profiling(void* ctx, int32_t enable) {
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_profile_collect(void* ctx, double* ms, int64_t* counts) {
+lbmletkf_status lbmletkf_profile_collect(lbmletkf_ctx* ctx, double* ms, int64_t* counts) {
     Ctx* c = as_ctx(ctx);
     if (!c || !ms || !counts) return fail(LBMLETKF_EINVAL, "NULL argument");
     for (int k = 0; k < LBMLETKF_NSTAGES; ++k) {
@@ -998,7 +1086,7 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
 };
 
-Batch* as_batch(void* b) { return reinterpret_cast<Batch*>(b); }
+Batch* as_batch(lbmletkf_batch* b) { return reinterpret_cast<Batch*>(b); }
 
 struct BatchLayout {
     size_t params, tasks, yo, groups, total, group_bytes;
@@ -1301,7 +1389,7 @@ lbmletkf_status batch_apply_config(Batch* b, const lbmletkf_batch_config* cfg, h
 
 extern "C" {
 
-lbmletkf_status lbmletkf_batch_workspace_bytes(void* const* ctxs, int32_t n, size_t* bytes) {
+lbmletkf_status lbmletkf_batch_workspace_bytes(lbmletkf_ctx* const* ctxs, int32_t n, size_t* bytes) {
     if (!ctxs || n < 1 || !bytes) return fail(LBMLETKF_EINVAL, "need n >= 1 contexts and bytes");
     std::vector<Ctx*> v;
     for (int k = 0; k < n; ++k) {
@@ -1312,10 +1400,10 @@ lbmletkf_status lbmletkf_batch_workspace_bytes(void* const* ctxs, int32_t n, siz
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32_t n,
+lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_f, int32_t n,
                                       int32_t nsteps, const lbmletkf_batch_config* cfg,
                                       void* d_workspace, size_t bytes, void* stream,
-                                      void** batch_out) {
+                                      lbmletkf_batch** batch_out) {
     if (!ctxs || !d_f || n < 1 || !batch_out) return fail(LBMLETKF_EINVAL, "NULL argument");
     *batch_out = nullptr;
     if (nsteps < 1) return fail(LBMLETKF_EINVAL, "nsteps must be >= 1");
@@ -1386,11 +1474,11 @@ lbmletkf_status lbmletkf_batch_create(void* const* ctxs, void* const* d_f, int32
         delete b;
         return st;
     }
-    *batch_out = b;
+    *batch_out = reinterpret_cast<lbmletkf_batch*>(b);
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_batch_destroy(void* batch) {
+lbmletkf_status lbmletkf_batch_destroy(lbmletkf_batch* batch) {
     Batch* b = as_batch(batch);
     if (!b) return fail(LBMLETKF_EINVAL, "batch is NULL");
     batch_release(b);
@@ -1398,7 +1486,7 @@ lbmletkf_status lbmletkf_batch_destroy(void* batch) {
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_batch_run_cycle(void* batch, const double* const* d_yo, void* stream) {
+lbmletkf_status lbmletkf_batch_run_cycle(lbmletkf_batch* batch, const double* const* d_yo, void* stream) {
     Batch* b = as_batch(batch);
     if (!b || !d_yo) return fail(LBMLETKF_EINVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
@@ -1412,21 +1500,21 @@ lbmletkf_status lbmletkf_batch_run_cycle(void* batch, const double* const* d_yo,
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "batch cycle");
 }
 
-lbmletkf_status lbmletkf_batch_get_config(void* batch, lbmletkf_batch_config* cfg) {
+lbmletkf_status lbmletkf_batch_get_config(lbmletkf_batch* batch, lbmletkf_batch_config* cfg) {
     Batch* b = as_batch(batch);
     if (!b || !cfg) return fail(LBMLETKF_EINVAL, "NULL argument");
     *cfg = b->cfg;
     return LBMLETKF_OK;
 }
 
-lbmletkf_status lbmletkf_batch_set_config(void* batch, const lbmletkf_batch_config* cfg,
+lbmletkf_status lbmletkf_batch_set_config(lbmletkf_batch* batch, const lbmletkf_batch_config* cfg,
                                           void* stream) {
     Batch* b = as_batch(batch);
     if (!b || !cfg) return fail(LBMLETKF_EINVAL, "NULL argument");
     return batch_apply_config(b, cfg, as_stream(stream));
 }
 
-lbmletkf_status lbmletkf_batch_tune(void* batch, int32_t reps, lbmletkf_batch_config* best,
+lbmletkf_status lbmletkf_batch_tune(lbmletkf_batch* batch, int32_t reps, lbmletkf_batch_config* best,
                                     double* forecast_ms, double* analysis_ms, void* stream) {
     Batch* b = as_batch(batch);
     if (!b || reps < 1) return fail(LBMLETKF_EINVAL, "need a batch and reps >= 1");

@@ -133,6 +133,7 @@ struct AnalysisParams {
     double rinv[3];       // 1 / sigma^2 per variable
     double a;             // (M - 1) / beta
     double sqrt_beta;
+    int max_sweeps;       // Jacobi sweep cap of the eigensolvers
     int* eig_fail;        // count of nodes whose eigensolver hit the sweep cap
     // cycle diagnostics folded into the analysis (NULL: none): per node the five
     // diagnostic fields (err2, spread2, non-finite, rho min, rho max) of the
@@ -183,6 +184,13 @@ hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int sto
                        double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_synth_obs(const double* y, const double* eps, const double* sigma, double* yo,
                             int n, hipStream_t s);
+
+// ---- energy spectrum (spectrum.hip) ----------------------------------------
+// Member-mean shell spectrum E[0..kmax] of the velocity of an n x n ensemble;
+// `scratch` holds spectrum_scratch_bytes(n, members) bytes (256-byte aligned).
+size_t spectrum_scratch_bytes(int n, int members);
+hipError_t launch_energy_spectrum(const void* f, int n, int members, int storage, int kmax,
+                                  void* scratch, double* E, hipStream_t s);
 
 // ---- differentiation form (adjoint.hip) -----------------------------------
 // One reverse step: lam_out = adjoint of the step taken from fstate (storage

@@ -155,7 +155,7 @@ __device__ __forceinline__ double group_sum(double v) {
 // problem, a segment of G = 64 / SEGS lanes per node, lane i of a segment =
 // member i; the segment's rows of A and U are its first N lanes.
 template <int N, typename T>
-__device__ __forceinline__ void ens_body(const AnalysisParams p, int node0, int max_sweeps) {
+__device__ __forceinline__ void ens_body(const AnalysisParams p, int node0) {
     constexpr int SEGS = ens_segs(N);
     constexpr int G = kWave / SEGS;
     T* __restrict__ fs = reinterpret_cast<T*>(p.f);
@@ -241,8 +241,8 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node0, int 
             for (int k = 0; k < N; ++k) S[k] += z * zr[sbase + k];
         }
     }
-    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, max_sweeps);
-    if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
+    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, p.max_sweeps);
+    if (sweeps > p.max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
     const double lam = extract_lane_entry<N>(S, i);
     const double psi = i < N ? 1.0 / lam : 0.0;
     const double mu = i < N ? sqrt((M - 1) / lam) : 0.0;
@@ -295,21 +295,20 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node0, int 
 }
 
 template <int N, typename T>
-__global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p, int max_sweeps) {
+__global__ __launch_bounds__(64) void analysis_ens_kernel(AnalysisParams p) {
     const int node0 = xcd_remap(blockIdx.x, gridDim.x) * ens_segs(N);
     if (node0 >= p.nx * p.ny) return;
-    ens_body<N, T>(p, node0, max_sweeps);
+    ens_body<N, T>(p, node0);
 }
 
 // Batched form: wavefront w takes waves[w] = (problem, node).
 template <int N, typename T>
 __global__ __launch_bounds__(64) void analysis_ens_batch_kernel(const AnalysisParams* P,
-                                                                const int2* waves, int nwaves,
-                                                                int max_sweeps) {
+                                                                const int2* waves, int nwaves) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     if (w >= nwaves) return;
     const int2 d = waves[w];  // (problem, first node of the wavefront's ens_segs(N) nodes)
-    ens_body<N, T>(P[d.x], d.y, max_sweeps);
+    ens_body<N, T>(P[d.x], d.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,7 +478,7 @@ hipError_t launch_ens_t(const AnalysisParams& p, hipStream_t s) {
                                            (int)bytes);
         if (e != hipSuccess) return e;
     }
-    analysis_ens_kernel<N, T><<<(plane + ens_segs(N) - 1) / ens_segs(N), 64, bytes, s>>>(p, 30);
+    analysis_ens_kernel<N, T><<<(plane + ens_segs(N) - 1) / ens_segs(N), 64, bytes, s>>>(p);
     return hipGetLastError();
 }
 
@@ -511,7 +510,7 @@ hipError_t launch_ens_batch_t(const AnalysisParams* P, const int2* waves, int nw
                                            (int)bytes);
         if (e != hipSuccess) return e;
     }
-    analysis_ens_batch_kernel<N, T><<<nwaves, 64, bytes, s>>>(P, waves, nwaves, 30);
+    analysis_ens_batch_kernel<N, T><<<nwaves, 64, bytes, s>>>(P, waves, nwaves);
     return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ __device__ __forceinline__ void local_obs(const AnalysisParams& p, int node, int
 // One wavefront: the nodes nodes[item0 + seg] (seg < SEGS, item < end) of one problem.
 template <int N>
 __device__ __forceinline__ void eig_body(const AnalysisParams p, const int* nodes, int item0,
-                                         int end, double* gout, int max_sweeps) {
+                                         int end, double* gout) {
     using L = EigLayout<N>;
     constexpr int SEGS = L::SEGS;
     constexpr int RS = L::RS;
@@ -109,8 +109,8 @@ __device__ __forceinline__ void eig_body(const AnalysisParams p, const int* node
             U[k] = (k == i && active) ? 1.0 : 0.0;
         }
     }
-    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, rows, lane, max_sweeps);
-    if (sweeps > max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
+    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, rows, lane, p.max_sweeps);
+    if (sweeps > p.max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
 
     // eigenvalue functions, U to LDS, t = U^T d~, h = U psi t, G = U phi U^T
     const double lam = extract_lane_entry<N>(S, i);
@@ -259,7 +259,7 @@ __device__ __forceinline__ void split_round(double (&S)[N / 2], double (&U)[N / 
 // One block of two wavefronts: node nodes[item] (item < end) of one problem.
 template <int N>
 __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int* nodes, int item,
-                                               int end, double* gout, int max_sweeps) {
+                                               int end, double* gout) {
     using L = SplitLayout<N>;
     constexpr int H = L::H;
     constexpr int RS = L::RS;
@@ -329,8 +329,8 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
             sd += red[2 * k + 1];
         }
         if (so <= 1e-26 * sd) break;
-        if (sweeps >= max_sweeps) {
-            sweeps = max_sweeps + 1;
+        if (sweeps >= p.max_sweeps) {
+            sweeps = p.max_sweeps + 1;
             break;
         }
         double2* mycs = cs + hh * N;
@@ -340,7 +340,7 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
             split_round<N, 1>(S, U, rows + N * RS, mycs, bx, i, hh, active);
         }
     }
-    if (sweeps > max_sweeps && t == 0) atomicAdd(p.eig_fail, 1);
+    if (sweeps > p.max_sweeps && t == 0) atomicAdd(p.eig_fail, 1);
 
     // eigenvalues (the diagonal entry of row i sits in half i / H), U to LDS
     __syncthreads();
@@ -418,13 +418,11 @@ constexpr int eig_lds_doubles() {
 
 template <int N>
 __global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
-void analysis_eig_kernel(AnalysisParams p, const int* nodes, int count, double* gout,
-                         int max_sweeps) {
+void analysis_eig_kernel(AnalysisParams p, const int* nodes, int count, double* gout) {
     if constexpr (kSplitRows<N>)
-        eig_body_split<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x), count, gout, max_sweeps);
+        eig_body_split<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x), count, gout);
     else
-        eig_body<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x) * EigLayout<N>::SEGS, count, gout,
-                    max_sweeps);
+        eig_body<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x) * EigLayout<N>::SEGS, count, gout);
 }
 
 // Batched form: wavefront w takes waves[w] = (problem, first item, end of the
@@ -432,13 +430,13 @@ void analysis_eig_kernel(AnalysisParams p, const int* nodes, int count, double* 
 template <int N>
 __global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
 void analysis_eig_batch_kernel(const AnalysisParams* P, const int4* waves, int nwaves,
-                               const int* nodes, double* gout, int max_sweeps) {
+                               const int* nodes, double* gout) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     if (w >= nwaves) return;
     const int4 d = waves[w];
     const AnalysisParams p = P[d.x];
-    if constexpr (kSplitRows<N>) eig_body_split<N>(p, nodes, d.y, d.z, gout, max_sweeps);
-    else eig_body<N>(p, nodes, d.y, d.z, gout, max_sweeps);
+    if constexpr (kSplitRows<N>) eig_body_split<N>(p, nodes, d.y, d.z, gout);
+    else eig_body<N>(p, nodes, d.y, d.z, gout);
 }
 
 // Dynamic LDS beyond 64 KiB needs the kernel's permission (set once per kernel).
@@ -653,7 +651,7 @@ hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double
     static bool lds_ok = false;
     hipError_t e = allow_lds(analysis_eig_kernel<N>, eig_bytes, &lds_ok);
     if (e != hipSuccess) return e;
-    analysis_eig_kernel<N><<<eig_blocks, eig_threads<N>(), eig_bytes, s>>>(p, nodes, count, gbuf, 30);
+    analysis_eig_kernel<N><<<eig_blocks, eig_threads<N>(), eig_bytes, s>>>(p, nodes, count, gbuf);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
@@ -674,7 +672,7 @@ hipError_t launch_batch_n(const AnalysisParams* d_params, const int4* d_eig_wave
     hipError_t e = allow_lds(analysis_eig_batch_kernel<N>, eig_bytes, &lds_ok);
     if (e != hipSuccess) return e;
     analysis_eig_batch_kernel<N><<<n_eig, eig_threads<N>(), eig_bytes, s>>>(
-        d_params, d_eig_waves, n_eig, d_nodes, gbuf, 30);
+        d_params, d_eig_waves, n_eig, d_nodes, gbuf);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
