@@ -174,6 +174,22 @@ lbmletkf_status letkf_analyze(lbmletkf_ctx* ctx, void* d_f, const double* d_yf, 
 lbmletkf_status lbmletkf_diagnostics(lbmletkf_ctx* ctx, const void* d_f, const double* d_truth_uv,
                                      double* d_diag, void* stream);
 
+/* Allocation-free variant of lbmletkf_diagnostics, for callers that cannot
+ * allocate device memory or hand over a workspace: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  It needs no
+ * context: lbm gives the grid, members and storage of d_f (the other fields
+ * are validated but unused).  Same kernels and output (bit for bit) as
+ * lbmletkf_diagnostics; the per-block partial sums go to a static device array
+ * of 4 MiB that the library holds on every GPU it runs on until the process
+ * ends, so grids of at most 6,710,848 nodes (LBMLETKF_ESHAPE beyond; 40 bytes
+ * per 64 nodes).  Calls no allocator.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams, threads) race;
+ * calls ordered on one stream do not.  The first call on a device resolves
+ * the array's address there. */
+lbmletkf_status lbmletkf_diagnostics_noalloc(const lbmletkf_lbm_params* lbm, const void* d_f,
+                                             const double* d_truth_uv, double* d_diag,
+                                             void* stream);
+
 /* One forecast-analysis cycle (Sec. 3 workflow (ii)-(iv)):
  * lbm_ensemble_step(nsteps) -> observe -> letkf_analyze.  d_yo: this
  * cycle's observations.  If d_diag is not NULL it receives the forecast

@@ -74,6 +74,7 @@ SIGNATURES = {
     "lbmletkf_diagnostics": (_c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "run_cycle": (_c_int32, [_vp, _vp, _c_int32, _vp, _vp, _vp, _vp]),
     "lbmletkf_moments": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "lbmletkf_diagnostics_noalloc": (_c_int32, [ctypes.POINTER(LbmParams), _vp, _vp, _vp, _vp]),
     "lbmletkf_set_checks": (_c_int32, [_vp, _c_int32, _c_double, _c_int32]),
     "lbmletkf_check": (_c_int32, [_vp, _vp, _vp]),
     "lbmletkf_energy_spectrum": (_c_int32, [_vp, _vp, _vp, _c_int32, _vp]),
@@ -295,6 +296,23 @@ def _params(nx, ny, members, tau0, cs, mu, points, nvar, sigma, d_cut, beta, rou
     obs = ObsParams(len(pts), pts.ctypes.data_as(ctypes.POINTER(_c_int32)), int(nvar),
                     (_c_double * 3)(*sig), dc, float(beta), int(route))
     return lbm, obs, pts
+
+
+def diagnostics_noalloc(nx: int, ny: int, members: int, f: torch.Tensor,
+                        truth_uv: Optional[torch.Tensor] = None,
+                        out: Optional[torch.Tensor] = None, storage: int = STORAGE_F64,
+                        stream=None) -> torch.Tensor:
+    """lbmletkf_diagnostics_noalloc: the ensemble diagnostics of f (storage
+    layout) without a context or workspace (static device scratch)."""
+    lbm = LbmParams(int(nx), int(ny), int(members), 0.6, 0.0, 0.0, int(storage))
+    dtype = torch.float32 if storage == STORAGE_F32_DEV else torch.float64
+    plane = int(nx) * int(ny)
+    if out is None:
+        out = torch.empty(DIAG_LEN, dtype=torch.float64, device=f.device)
+    _check(load().lbmletkf_diagnostics_noalloc(
+        ctypes.byref(lbm), _dev(f, members * 9 * plane, "f", dtype),
+        _dev(truth_uv, 2 * plane, "truth_uv"), _dev(out, DIAG_LEN, "diag"), _stream(stream)))
+    return out
 
 
 def synth_obs(y: torch.Tensor, eps: torch.Tensor, sigma: torch.Tensor, stream=None) -> torch.Tensor:

@@ -733,6 +733,29 @@ lbmletkf_status lbmletkf_diagnostics(lbmletkf_ctx* ctx, const void* d_f, const d
     return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics");
 }
 
+lbmletkf_status lbmletkf_diagnostics_noalloc(const lbmletkf_lbm_params* lbm, const void* d_f,
+                                             const double* d_truth_uv, double* d_diag,
+                                             void* stream) {
+    lbmletkf_status st = check_lbm(lbm);
+    if (st) return st;
+    if (!d_f || !d_diag) return fail(LBMLETKF_EINVAL, "NULL argument");
+    const int plane = lbm->nx * lbm->ny;
+    if (diag_partial_bytes(plane) > kStaticScratchBytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg,
+                      "a grid of %d nodes needs %zu bytes of scratch; the static scratch holds %zu",
+                      plane, diag_partial_bytes(plane), kStaticScratchBytes);
+        return fail(LBMLETKF_ESHAPE, msg);
+    }
+    void* scratch = nullptr;
+    hipError_t e = static_scratch(&scratch);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    e = launch_diag(d_f, d_truth_uv, {lbm->nx, lbm->ny, lbm->members}, lbm->storage,
+                    reinterpret_cast<double*>(scratch), diag_blocks_for(plane), d_diag,
+                    as_stream(stream));
+    return e == hipSuccess ? LBMLETKF_OK : hip_fail(e, "diagnostics_noalloc");
+}
+
 lbmletkf_status run_cycle(lbmletkf_ctx* ctx, void* d_f, int32_t nsteps, const double* d_yo,
                           const double* d_truth_uv, double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);

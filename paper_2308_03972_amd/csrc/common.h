@@ -179,6 +179,13 @@ hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4*
                                      const int* d_nodes, int n, double* gbuf, int storage,
                                      hipStream_t s);
 int diag_blocks_for(int plane);
+// Bytes of diag_partial_kernel's per-block records for a grid of `plane` nodes.
+size_t diag_partial_bytes(int plane);
+// The static device scratch (kStaticScratchBytes) of the allocation-free
+// entry point: its device address on the current device, resolved once per
+// device (hipGetSymbolAddress) and kept.
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+hipError_t static_scratch(void** addr);
 
 hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int storage,
                        double* partial, int nblocks, double* out, hipStream_t s);

@@ -21,8 +21,15 @@
 // i of the matrix and of the eigenvector matrix in registers; each round
 // rotates the neighbour pairs (2k+p, 2k+p+1) and swaps them, so two fixed
 // pairings alternate and every pair meets once per n rounds.
+#include <mutex>
+
 #include "common.h"
 #include "device_util.h"
+
+// Device scratch of the allocation-free diagnostics entry point: the per-block
+// partial records of diag_partial_kernel.  Every GPU the library runs on holds
+// its own copy until the process ends; all calls on one GPU share it.
+static __device__ __align__(256) double scratch[lbmletkf::kStaticScratchBytes / sizeof(double)];
 
 namespace lbmletkf {
 namespace {
@@ -582,6 +589,34 @@ hipError_t launch_analysis_ens(const AnalysisParams& p, int n, hipStream_t s) {
 }
 
 int diag_blocks_for(int plane) { return (plane + kDiagNodes - 1) / kDiagNodes; }
+
+size_t diag_partial_bytes(int plane) {
+    return (size_t)diag_blocks_for(plane) * kDiagFields * sizeof(double);
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** addr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        // the array's device address on the current device (its host-side name
+        // is not a device pointer)
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *addr = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_diag(const void* f, const double* truth_uv, LbmDims d, int storage,
                        double* partial, int nblocks, double* out, hipStream_t s) {
