@@ -675,7 +675,7 @@ lbmletkf_status analyze_impl(Ctx* c, void* d_f, const double* d_yf, const double
     {
         StageTimer t(c, kStageStats, s);
         hipError_t e = launch_obs_stats(d_yf, d_yo, c->nobs, c->dims.members, c->ybar(), c->dY(),
-                                        c->dvec(), c->K(), s);
+                                        c->dvec(), c->K(), c->storage(), s);
         if (e != hipSuccess) return hip_fail(e, "obs_stats");
     }
     AnalysisParams p = make_params(c, d_f);
@@ -1346,7 +1346,7 @@ hipError_t batch_observe(Batch* b, bool partners, hipStream_t s) {
                            b->storage, s);
         if (e == hipSuccess)
             e = launch_obs_stats(c->yf(), b->d_yo + b->yo_off[k], c->nobs, c->dims.members,
-                                 c->ybar(), c->dY(), c->dvec(), c->K(), s);
+                                 c->ybar(), c->dY(), c->dvec(), c->K(), b->storage, s);
     }
     return e;
 }

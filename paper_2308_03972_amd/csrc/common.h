@@ -115,8 +115,11 @@ hipError_t launch_moments(const void* f, double* out, LbmDims d, int storage, hi
 // ---- observation, statistics, analysis, diagnostics (letkf_kernels.hip) ---
 hipError_t launch_observe(const void* f, const int* pts, int npts, int nvar, double* yf,
                           LbmDims d, int storage, hipStream_t s);
+// y_bar, dY, d = y^o - y_bar and (K != NULL) the Gram matrix K = dY dY^T on the
+// matrix cores: FP64 MFMA, or FP32 MFMA for the precision form's storage.
 hipError_t launch_obs_stats(const double* yf, const double* yo, int nobs, int members,
-                            double* ybar, double* dY, double* dvec, double* K, hipStream_t s);
+                            double* ybar, double* dY, double* dvec, double* K, int storage,
+                            hipStream_t s);
 hipError_t launch_local_table(const int* pts, int npts, double d_cut, int lmax, int nx, int ny,
                               int* loc_pt, double* loc_g, int* overflow, hipStream_t s);
 

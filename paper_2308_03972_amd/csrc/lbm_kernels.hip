@@ -73,6 +73,50 @@ __device__ __forceinline__ void collide_node(double (&f)[9], double tau0, double
     }
 }
 
+// The same relaxation in FP32 on the deviations g_a = f_a - w_a that FP32
+// storage keeps (the precision form): the lattice sums of the weights are
+// exact constants (sum w = 1, sum w c = 0, sum w c c = I/3), so every moment
+// is a sum of small numbers, rho = 1 + sum g,
+//   Pi_xx = sum c_x^2 g - (rho - 1)/3 - rho u^2,  Pi_xy = sum c_x c_y g - rho u v,
+//   g^eq_a = w_a [(rho - 1) + rho (3 cu + 4.5 cu^2 - 1.5 u.u)],
+// and FP32 keeps ~7 significant digits of quantities of size |g| <~ 0.02.
+__device__ __forceinline__ float cdotf(int a, float x, float y) {
+    const int cx = cx_of(a), cy = cy_of(a);
+    const float tx = cx > 0 ? x : (cx < 0 ? -x : 0.0f);
+    if (cy == 0) return tx;
+    if (cx == 0) return cy > 0 ? y : -y;
+    return cy > 0 ? tx + y : tx - y;
+}
+
+__device__ __forceinline__ void collide_node_dev(float (&g)[9], float tau0, float smag,
+                                                 float fx_ext, float fy_ext, float mu) {
+#pragma clang fp contract(off)
+    const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float rho = 1.0f + drho;
+    const float jx = (g[1] - g[2]) + (g[5] - g[6]) + (g[7] - g[8]);
+    const float jy = (g[3] - g[4]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const float inv_rho = 1.0f / rho;
+    const float u = jx * inv_rho, v = jy * inv_rho;
+    const float uu = u * u, vv = v * v, uv = u * v;
+    const float d3 = drho * (1.0f / 3.0f);
+    const float pxx = fmaf(-rho, uu, (g[1] + g[2] + g[5] + g[6] + g[7] + g[8]) - d3);
+    const float pyy = fmaf(-rho, vv, (g[3] + g[4] + g[5] + g[6] + g[7] + g[8]) - d3);
+    const float pxy = fmaf(-rho, uv, g[5] + g[6] - g[7] - g[8]);
+    const float pn = sqrtf(fmaf(pxx, pxx, fmaf(pyy, pyy, (2.0f * pxy) * pxy)));
+    const float tau = 0.5f * (tau0 + sqrtf(fmaf(tau0, tau0, (smag * pn) * inv_rho)));
+    const float omega = 1.0f / tau;
+    const float gx = fmaf(-mu, u, fx_ext), gy = fmaf(-mu, v, fy_ext);
+    const float usq = -1.5f * (uu + vv);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const float w = (float)w_of(a);
+        const float cu = cdotf(a, u, v);
+        const float geq = w * fmaf(rho, fmaf(cu, fmaf(4.5f, cu, 3.0f), usq), drho);
+        const float Fa = (3.0f * w * rho) * cdotf(a, gx, gy);
+        g[a] = fmaf(-omega, g[a] - geq, g[a] + Fa);
+    }
+}
+
 // V consecutive members per thread: FP32 deviations move 4 bytes per member,
 // and one 8-byte access per population for two members keeps the wavefront's
 // requests as wide as in FP64.
@@ -93,38 +137,51 @@ __device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restr
     // node holding the canonical f_a(x, y): (x - c_ax, y - c_ay)
     const size_t src[9] = {rc + x,  rc + xm, rc + xp, rm + x, rp + x,
                            rm + xm, rp + xp, rp + xm, rm + xp};
-    // every population is read once and written once per step: stream it
-    // past the caches (nontemporal loads and stores)
-    double f[V][9];
-    if constexpr (V == 1) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) f[0][a] = PopIO<T>::load_nt(fin + slot(src[a], a, m, members), a);
-    } else {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const float2v g = __builtin_nontemporal_load(
-                reinterpret_cast<const float2v*>(fin + slot(src[a], a, m, members)));
-            f[0][a] = w_of(a) + (double)g.x;
-            f[1][a] = w_of(a) + (double)g.y;
-        }
-    }
     double fx = 0.0, fy = 0.0;
     if (force) {
         fx = force[node];
         fy = force[plane + node];
     }
+    // every population is read once and written once per step: stream it
+    // past the caches (nontemporal loads and stores)
+    if constexpr (sizeof(T) == 8) {
+        double f[9];
 #pragma unroll
-    for (int k = 0; k < V; ++k) collide_node(f[k], tau0, smag, fx, fy, mu);
-    if constexpr (V == 1) {
+        for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(fin + slot(src[a], a, m, members), a);
+        collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[0][a]);
+        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
     } else {
+        // FP32 deviations: the FP32 relaxation on g = f - w, no conversion
+        float g[V][9];
+        if constexpr (V == 1) {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            float2v g;
-            g.x = (float)(f[0][a] - w_of(a));
-            g.y = (float)(f[1][a] - w_of(a));
-            __builtin_nontemporal_store(g, reinterpret_cast<float2v*>(fout + slot(node, a, m, members)));
+            for (int a = 0; a < 9; ++a)
+                g[0][a] = __builtin_nontemporal_load(fin + slot(src[a], a, m, members));
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const float2v p = __builtin_nontemporal_load(
+                    reinterpret_cast<const float2v*>(fin + slot(src[a], a, m, members)));
+                g[0][a] = p.x;
+                g[1][a] = p.y;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            collide_node_dev(g[k], (float)tau0, (float)smag, (float)fx, (float)fy, (float)mu);
+        if constexpr (V == 1) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                __builtin_nontemporal_store(g[0][a], fout + slot(node, a, m, members));
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                float2v p;
+                p.x = g[0][a];
+                p.y = g[1][a];
+                __builtin_nontemporal_store(p, reinterpret_cast<float2v*>(fout + slot(node, a, m, members)));
+            }
         }
     }
 }
@@ -348,35 +405,27 @@ hipError_t launch_stream_collide(const void* fin, void* fout, const double* forc
 }
 
 bool two_step_supported(LbmDims d, int storage) {
-    // FP32 storage keeps one step per launch: its two-members-per-thread step is faster
+    // FP32 storage keeps one step per launch (its FP32 relaxation on two members
+    // per thread); the tiled two-step kernel is the FP64 form's
     return storage == kStoreF64 && d.members % kTwoMG == 0;
 }
 
 hipError_t launch_stream_collide2(const void* fin, void* fout, const double* force, LbmDims d,
                                   double tau0, double cs, double mu, int storage, hipStream_t s) {
+    if (!two_step_supported(d, storage)) return hipErrorInvalidValue;
     const int tiles = ((d.nx + kTwoT - 1) / kTwoT) * ((d.ny + kTwoT - 1) / kTwoT);
     const dim3 grid(tiles * (d.members / kTwoMG)), block(kTwoMG, kTwoR * kTwoR);
     const size_t bytes = (size_t)two_step_lds_doubles() * sizeof(double);
     const double smag = 18.0 * sqrt(2.0) * cs * cs;
-    static bool attr64 = false, attr32 = false;
+    static bool attr = false;
     hipError_t e = hipSuccess;
-    if (storage == kStoreF32Dev) {
-        if (!attr32)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel<float>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        attr32 = true;
-        stream_collide2_kernel<float><<<grid, block, bytes, s>>>(
-            (const float*)fin, (float*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
-    } else {
-        if (!attr64)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel<double>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        attr64 = true;
-        stream_collide2_kernel<double><<<grid, block, bytes, s>>>(
-            (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
-    }
+    if (!attr)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+    stream_collide2_kernel<double><<<grid, block, bytes, s>>>(
+        (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
     return hipGetLastError();
 }
 

@@ -83,17 +83,61 @@ __global__ __launch_bounds__(256) void obs_stats_kernel(
     }
 }
 
-// K = dY dY^T (unweighted observation-space Gram matrix)
-__global__ void obs_gram_kernel(const double* __restrict__ dY, int nobs, int members,
-                                double* __restrict__ K) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nobs * nobs) return;
-    const int q = t / nobs, r = t - q * nobs;
-    const double* a = dY + (size_t)q * members;
-    const double* b = dY + (size_t)r * members;
-    double s = 0.0;
-    for (int m = 0; m < members; ++m) s += a[m] * b[m];
-    K[t] = s;
+// K = dY dY^T (unweighted observation-space Gram matrix, nobs x nobs, inner
+// dimension the members): the dense contraction under every node's
+// Z Z^T = diag(sqrt r) K_L diag(sqrt r), on the matrix cores.  One wavefront
+// per 16 x 16 tile of K, the member dimension in steps of 4 through
+// v_mfma_{f64,f32}_16x16x4 (lane l supplies A[l % 16][l / 16] =
+// dY[q0 + l % 16][m0 + l / 16] and B[l / 16][l % 16] = dY[r0 + l % 16][m0 + l / 16];
+// result register j < 4 of lane l holds D[l / 16 + 4 j][l % 16] for the FP64
+// instruction and D[4 (l / 16) + j][l % 16] for the FP32 one, as measured on
+// gfx950 with lane-numbered operands).  Only tiles on or above the
+// diagonal are computed; each value is written to both (q, r) and (r, q), so K
+// is exactly symmetric.  T = double: FP64 MFMA (FP64 storage); T = float: FP32
+// MFMA on dY rounded to FP32, FP32 accumulation (the precision form).
+typedef double double4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(64) void obs_gram_kernel(const double* __restrict__ dY, int nobs,
+                                                      int members, double* __restrict__ K) {
+    const int tx = blockIdx.x, ty = blockIdx.y;
+    if (ty > tx) return;  // uniform over the wavefront
+    const int lane = threadIdx.x;
+    const int i = lane & 15, kq = lane >> 4;
+    const int qa = ty * 16 + i, rb = tx * 16 + i;
+    const bool qin = qa < nobs, rin = rb < nobs;
+    const double* arow = dY + (size_t)(qin ? qa : 0) * members;
+    const double* brow = dY + (size_t)(rin ? rb : 0) * members;
+    double out[4];
+    if constexpr (sizeof(T) == 8) {
+        double4v acc = {0.0, 0.0, 0.0, 0.0};
+        for (int m0 = 0; m0 < members; m0 += 4) {
+            const int m = m0 + kq;
+            const double a = (qin && m < members) ? arow[m] : 0.0;
+            const double b = (rin && m < members) ? brow[m] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[j] = acc[j];
+    } else {
+        float4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int m0 = 0; m0 < members; m0 += 4) {
+            const int m = m0 + kq;
+            const float a = (qin && m < members) ? (float)arow[m] : 0.0f;
+            const float b = (rin && m < members) ? (float)brow[m] : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[j] = (double)acc[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int row = ty * 16 + (sizeof(T) == 8 ? kq + 4 * j : 4 * kq + j), col = tx * 16 + i;
+        if (row >= nobs || col >= nobs || (tx == ty && row > col)) continue;
+        K[(size_t)row * nobs + col] = out[j];
+        K[(size_t)col * nobs + row] = out[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -567,12 +611,16 @@ hipError_t launch_observe(const void* f, const int* pts, int npts, int nvar, dou
 }
 
 hipError_t launch_obs_stats(const double* yf, const double* yo, int nobs, int members,
-                            double* ybar, double* dY, double* dvec, double* K, hipStream_t s) {
+                            double* ybar, double* dY, double* dvec, double* K, int storage,
+                            hipStream_t s) {
     obs_stats_kernel<<<(nobs + 3) / 4, 256, 0, s>>>(yf, yo, nobs, members, ybar, dY, dvec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !K) return e;
-    const int total = nobs * nobs;
-    obs_gram_kernel<<<(total + 255) / 256, 256, 0, s>>>(dY, nobs, members, K);
+    const int tiles = (nobs + 15) / 16;
+    if (storage == kStoreF32Dev)
+        obs_gram_kernel<float><<<dim3(tiles, tiles), 64, 0, s>>>(dY, nobs, members, K);
+    else
+        obs_gram_kernel<double><<<dim3(tiles, tiles), 64, 0, s>>>(dY, nobs, members, K);
     return hipGetLastError();
 }
 

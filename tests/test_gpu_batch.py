@@ -100,6 +100,8 @@ def test_batch_reproduces_each_problems_run_cycle(storage):
     probs = _setup(_mixed_configs(), storage, cycles=3)
     single = _single_runs(probs, 3)
     batched = _batch_runs(probs, 3)
+    diffs = [float(np.max(np.abs(s.astype(np.float64) - b))) for s, b in zip(single, batched)]
+    say(f"  max |batched - single| per problem: {diffs}")
     for s, b in zip(single, batched):
         assert np.array_equal(s, b)
 

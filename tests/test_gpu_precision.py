@@ -1,11 +1,17 @@
 """GPU parity of the precision form: populations stored as FP32 deviations
-f - w (LBMLETKF_F32_DEV), all arithmetic FP64.
+g = f - w (LBMLETKF_F32_DEV); the forecast relaxes g in FP32 arithmetic
+(rho = 1 + sum g), the analysis works in FP64.
 
-Tolerances: storing a deviation g = f - w (|g| <~ 0.02 here) in FP32 rounds it by
-|g| * 2^-24 <= 1.2e-9, so single steps and single analyses from an identical
-(already rounded) state agree with the FP64 oracle to ~1e-9 absolute; over a
-run the velocity RMSE must stay within 1e-3 of the observation-error standard
-deviation sigma (|dRMSE| < 1e-3 sigma = 2.9e-6) of the FP64 result.
+Tolerances: storing a deviation (|g| <~ 0.02 here) in FP32 rounds it by
+|g| 2^-24 <= 1.2e-9.  The FP32 relaxation adds a few FP32 roundings of
+quantities no larger than the state's largest deviation max|g| (the moments,
+the equilibrium deviation, the non-equilibrium part), multiplied by at most
+omega = 1/tau < 2: one step from an identical (already rounded) state agrees
+with the FP64 oracle to 32 * 2^-24 * max|g| (a generous count of roundings; a
+wrong term would miss by ~1e-4 and more).  A single analysis from an identical
+state (FP64 arithmetic) agrees to ~1e-9 absolute.  Over a run the velocity
+RMSE must stay within 1e-3 of the observation-error standard deviation sigma
+(|dRMSE| < 1e-3 sigma = 2.9e-6) of the FP64 result.
 """
 import numpy as np
 import pytest
@@ -65,7 +71,11 @@ def test_f32_stream_collide_step_matches_oracle(members):
     ctx.step(f, 1)
     got = host(ctx.export_canonical(f))
     ref = oracle.lbm_steps(start, 1, 0.55, 0.15, force)
-    assert np.max(np.abs(got - ref)) < 2e-9
+    w = oracle.lattice()[2][None, :, None, None]
+    gmax = np.max(np.abs(start - w))
+    err = np.max(np.abs(got - ref))
+    say(f"  max error {err:.2e} = {err / (2.0**-24 * gmax):.2f} x 2^-24 max|g|")
+    assert err < 32 * 2.0**-24 * gmax
 
 
 @pytest.mark.parametrize("route", [binding.ROUTE_ENSEMBLE, binding.ROUTE_OBSERVATION])
