@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import mmap
 import os
 import sys
 import time
@@ -82,10 +83,12 @@ _CPU_JOB = {}
 
 
 def _cpu_analysis_chunk(nodes):
+    """Worker: the oracle analysis of `nodes`, written into the shared output."""
     import oracle
     j = _CPU_JOB
-    return oracle.letkf_analysis(j["f"], j["yf"], j["yo"], j["pts"], j["sigmas"], j["d_cut"],
-                                 j["beta"], nodes=nodes)
+    j["out"][:, :, nodes] = oracle.letkf_analysis(j["f"], j["yf"], j["yo"], j["pts"], j["sigmas"],
+                                                  j["d_cut"], j["beta"], nodes=nodes)
+    return len(nodes)
 
 
 def cpu_baseline(cfg, force, pts, sample_cycles: int, procs: int):
@@ -108,12 +111,17 @@ def cpu_baseline(cfg, force, pts, sample_cycles: int, procs: int):
         t_lbm += time.perf_counter() - t0
         yf = oracle.observe(fe, pts, cfg.nvar)
         t0 = time.perf_counter()
+        # the workers (forked) write into a shared anonymous mapping
+        shared = mmap.mmap(-1, fe.nbytes)
+        out = np.frombuffer(shared, dtype=np.float64).reshape(cfg.members, 9, cfg.n * cfg.n)
         _CPU_JOB.update(f=fe, yf=yf, yo=yf.mean(axis=0), pts=pts, sigmas=cfg.sigmas,
-                        d_cut=cfg.d_cut, beta=cfg.beta)
+                        d_cut=cfg.d_cut, beta=cfg.beta, out=out)
         with mp.get_context("fork").Pool(procs) as pool:
-            parts = pool.map(_cpu_analysis_chunk, np.array_split(nodes, 8 * procs))
-        fe = np.concatenate(parts, axis=2).reshape(fe.shape)
+            pool.map(_cpu_analysis_chunk, np.array_split(nodes, 8 * procs))
+        fe = out.reshape(fe.shape).copy()
         _CPU_JOB.clear()
+        del out
+        shared.close()
         t_an += time.perf_counter() - t0
     t_cycle = (t_lbm + t_an) / sample_cycles
     # one LBM step on one thread, and one node's analysis in this process

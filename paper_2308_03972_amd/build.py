@@ -30,6 +30,10 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     os.makedirs(objdir, exist_ok=True)
     flags = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # matrix-core accumulators in ordinary VGPRs: the analysis kernels use
+             # MFMA only in a short phase, and reserved AGPRs would cost occupancy
+             # in the rest of the kernel
+             "-mllvm", "-amdgpu-mfma-vgpr-form=1",
              "-I", os.path.join(ROOT, "include")]
     procs, objs = [], []
     for src in SOURCES:

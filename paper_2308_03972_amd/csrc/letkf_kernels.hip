@@ -22,6 +22,7 @@
 // rotates the neighbour pairs (2k+p, 2k+p+1) and swaps them, so two fixed
 // pairings alternate and every pair meets once per n rounds.
 #include <mutex>
+#include <type_traits>
 
 #include "common.h"
 #include "device_util.h"
@@ -98,6 +99,20 @@ __global__ __launch_bounds__(256) void obs_stats_kernel(
 typedef double double4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
+// One 16 x 16 x 4 matrix-core product, D = A B + C, in the precision of T.
+__device__ __forceinline__ double4v mfma16(double a, double b, double4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float4v mfma16(float a, float b, float4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row of D held in result register j of lane l (column l % 16): FP64 and FP32
+// instructions spread the rows differently.
+template <typename T>
+__device__ __forceinline__ int mfma16_row(int lane, int j) {
+    return sizeof(T) == 8 ? (lane >> 4) + 4 * j : 4 * (lane >> 4) + j;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void obs_gram_kernel(const double* __restrict__ dY, int nobs,
                                                       int members, double* __restrict__ K) {
@@ -133,7 +148,7 @@ __global__ __launch_bounds__(64) void obs_gram_kernel(const double* __restrict__
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int row = ty * 16 + (sizeof(T) == 8 ? kq + 4 * j : 4 * kq + j), col = tx * 16 + i;
+        const int row = ty * 16 + mfma16_row<T>(lane, j), col = tx * 16 + i;
         if (row >= nobs || col >= nobs || (tx == ty && row > col)) continue;
         K[(size_t)row * nobs + col] = out[j];
         K[(size_t)col * nobs + row] = out[j];
@@ -202,6 +217,86 @@ __device__ __forceinline__ double group_sum(double v) {
     return group_reduce<G>(v, OpAdd());
 }
 
+// Z^T Z of the SEGS nodes of a wavefront on the matrix cores (N a multiple of
+// 16): Z = R_loc^-1/2 dY restricted to each node's local observations (nz x M,
+// members padded with zeros to N).  Per node the N x N product is NB x NB tiles
+// of 16 x 16 (NB = N / 16), of which the NB (NB + 1) / 2 on or above the
+// diagonal are accumulated over the observations in steps of 4 (lane l loads
+// Z[j0 + l / 16][16 b + l % 16] once per member block b and feeds it as both
+// operands: A = Z^T and B = Z carry the same numbers); the tiles go to the
+// segment's rows in LDS, mirrored, and lane i of each segment returns row i of
+// a I + Z^T Z.  MT: the matrix-core precision (double: FP64 MFMA; float: FP32
+// MFMA with FP32 accumulation).  `obs` points at segment 0's weights, innovations
+// and observation indices; segment s's are `seg_stride` doubles further.
+template <int N, int SEGS, typename MT>
+__device__ __forceinline__ void ens_gram_mfma(const AnalysisParams& p, const double* obs,
+                                              int seg_stride, int nzp, int nz, double* rows,
+                                              int lane, int seg, int i, double (&S)[N]) {
+    static_assert(N % 16 == 0, "matrix-core tiles of 16");
+    constexpr int NB = N / 16;
+    constexpr int NT = NB * (NB + 1) / 2;
+    constexpr int RS = RowStride<N>::value;
+    using Acc = typename std::conditional<sizeof(MT) == 8, double4v, float4v>::type;
+    const int M = p.members;
+    const int kq = lane >> 4, c = lane & 15;
+    Acc acc[SEGS][NT];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[s][t] = Acc{0, 0, 0, 0};
+    for (int j0 = 0; j0 < nz; j0 += 4) {
+        const int jj = j0 + kq;
+        const bool jin = jj < nz;
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s) {
+            const double* sw_s = obs + (size_t)s * seg_stride;
+            const int* qx_s = reinterpret_cast<const int*>(sw_s + 2 * nzp);
+            const double w = jin ? sw_s[jj] : 0.0;
+            const double* yrow = p.dY + (size_t)(jin ? qx_s[jj] : 0) * M;
+            // unconditional loads (member 0 past the ensemble), selected afterwards
+            double y[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) y[b] = yrow[16 * b + c < M ? 16 * b + c : 0];
+            MT z[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) z[b] = (MT)((jin && 16 * b + c < M) ? w * y[b] : 0.0);
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+                for (int J = I; J < NB; ++J) {
+                    acc[s][t] = mfma16(z[I], z[J], acc[s][t]);
+                    ++t;
+                }
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        double* rs = rows + (size_t)s * N * RS;
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+            for (int J = I; J < NB; ++J, ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int R = 16 * I + mfma16_row<MT>(lane, j), C = 16 * J + c;
+                    if (I == J && R > C) continue;
+                    const double v = (double)acc[s][t][j];
+                    rs[(size_t)R * RS + C] = v;
+                    rs[(size_t)C * RS + R] = v;
+                }
+    }
+    wave_lds_sync();
+    const double* mine = rows + (size_t)(seg < SEGS ? seg : 0) * N * RS;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double v = (seg < SEGS && i < N) ? mine[(size_t)i * RS + k] : 0.0;
+        S[k] = (k == i) ? p.a + v : v;
+    }
+}
+
 // One wavefront: nodes node0 .. node0 + SEGS - 1 (those < nx * ny) of one
 // problem, a segment of G = 64 / SEGS lanes per node, lane i of a segment =
 // member i; the segment's rows of A and U are its first N lanes.
@@ -264,16 +359,30 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node0) {
     wave_lds_sync();
     // A = a I + Z^T Z and g = Z^T d~
     double S[N], U[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        S[k] = (k == i) ? p.a : 0.0;
-        U[k] = (k == i) ? 1.0 : 0.0;
-    }
     double g = 0.0;
+    constexpr int kZc = 8;
+    if constexpr (N % 16 == 0) {
+        // Z^T Z on the matrix cores (FP64 MFMA for FP64 storage, FP32 MFMA for
+        // the precision form), g on the vector units
+        ens_gram_mfma<N, SEGS, T>(p, zr + 64, 2 * nzp + nzp / 2, nzp, nz, rows, lane, seg, i, S);
+        for (int j0 = 0; j0 < nz; j0 += kZc) {
+            double zc[kZc];
+#pragma unroll
+            for (int t = 0; t < kZc; ++t)
+                zc[t] = p.dY[(size_t)qx[min(j0 + t, nz - 1)] * M + (mem ? i : 0)];
+#pragma unroll
+            for (int t = 0; t < kZc; ++t) {
+                const int j = j0 + t;
+                if (j >= nz) break;  // uniform over the wavefront
+                g += (mem ? sw[j] * zc[t] : 0.0) * dt[j];
+            }
+        }
+    } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) S[k] = (k == i) ? p.a : 0.0;
     // the perturbations are loaded eight observations at a time, unconditionally
     // (a non-member lane reads member 0), so that the loads of a chunk are in
     // flight together; the sums run in observation order
-    constexpr int kZc = 8;
     for (int j0 = 0; j0 < nz; j0 += kZc) {
         double zc[kZc];
 #pragma unroll
@@ -292,6 +401,9 @@ __device__ __forceinline__ void ens_body(const AnalysisParams p, int node0) {
             for (int k = 0; k < N; ++k) S[k] += z * zr[sbase + k];
         }
     }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) U[k] = (k == i) ? 1.0 : 0.0;
     const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, red, lane, p.max_sweeps);
     if (sweeps > p.max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
     const double lam = extract_lane_entry<N>(S, i);

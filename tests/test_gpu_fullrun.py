@@ -182,9 +182,13 @@ def test_twelve_problem_batch_against_the_oracle(storage):
         got = host(ctx.export_canonical(states[k])).reshape(cfg.members, 9, -1)[:, :, nodes]
         ref = g[f"p{k}_final_f"]
         err = float(np.max(np.abs(got - ref)))
-        # FP64: rounding only; FP32 deviations: each stored value carries <= |f - w| 2^-24
-        # (~1e-9) from each of the 40 steps and 2 analyses, damped by the collision
-        tol = 1e-12 if storage == binding.STORAGE_F64 else 5e-8
-        assert err < tol, (k, err)
+        # FP64: rounding only.  FP32 deviations: the FP32 relaxation of each step
+        # is within 32 2^-24 max|f - w| of the FP64 step (test_gpu_precision), and
+        # the 2 x 20 steps can add up at most linearly (the analyses, in FP64,
+        # add only the storage rounding)
+        w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[None, :, None]
+        gmax = float(np.max(np.abs(ref - w)))
+        tol = 1e-12 if storage == binding.STORAGE_F64 else cycles * cfg.steps_per_cycle * 32 * 2.0**-24 * gmax
+        assert err < tol, (k, err, tol)
     say(f"  per-problem max relative RMSE_a difference {max(worst.values()):.2e}")
     batch.close()
