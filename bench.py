@@ -302,8 +302,11 @@ def precision_config_form(cycles: int):
                         f"(u,v) observations, s={cfg.steps_per_cycle}, r={cfg.loc_r:g}, "
                         f"{cycles} cycles ({warmup} warmup)")}
     res = {}
-    for name, storage in (("plain", binding.STORAGE_F64), ("f32_dev", binding.STORAGE_F32_DEV)):
+    for name, storage, mfma in (("plain", binding.STORAGE_F64, False),
+                                ("f32_dev", binding.STORAGE_F32_DEV, False),
+                                ("f32_dev_mfma_transform", binding.STORAGE_F32_DEV, True)):
         ctx = binding.Context.from_config(cfg, force=force, storage=storage)
+        ctx.set_matrix_core_transform(mfma)
         runs, _ = run_form(ctx, cfg, yo_all, tuv_all, warmup, steps, 1, breakdown_cycles=1)
         el, d, ms, n = runs[0]
         res[name] = (el, d)
@@ -315,6 +318,8 @@ def precision_config_form(cycles: int):
             out[f"{name}_vs_fp64_oracle"] = versus_oracle(g, dall, spec, cfg.n, cycles)
         ctx.close()
     out["speedup_vs_plain"] = round(res["plain"][0] / res["f32_dev"][0], 4)
+    out["mfma_transform_speedup_vs_f32_dev"] = round(res["f32_dev"][0]
+                                                     / res["f32_dev_mfma_transform"][0], 4)
     out["max_abs_rmse_a_diff_vs_plain"] = float(np.max(np.abs(
         res["f32_dev"][1][:, binding.DIAG_LEN] - res["plain"][1][:, binding.DIAG_LEN])))
     out["tolerance_1e-3_sigma"] = 1e-3 * cfg.sigma
@@ -594,7 +599,8 @@ def main() -> int:
             forms[name] = differentiation_form(args.grad_reps, st)
             log(f"{name}: {forms[name]['ms_per_gradient']} ms per gradient")
         forms["f32_dev"] = {
-            "storage": "FP32 f - w, FP64 arithmetic",
+            "storage": ("FP32 f - w; FP32 relaxation; Gram matrices on FP32 matrix cores; "
+                        "FP64 eigensolve, weights and apply"),
             "cycles_per_s": round(args.steps / el32, 3),
             "speedup_vs_plain": round(elapsed / el32, 4),
             "stream_collide_us_per_step": round(1e3 * ms32[0] / max(n32[0], 1), 2),

@@ -71,8 +71,11 @@ typedef enum {
 /* Storage of the populations in every state buffer d_f:
  *   F64      FP64 values f_a;
  *   F32_DEV  FP32 deviations f_a - w_a from the lattice weights (the precision
- *            form: half the bytes per step; all arithmetic stays FP64).
- * Canonical buffers (import/export) are always FP64 values f_a. */
+ *            form: half the bytes per step).
+ * Canonical buffers (import/export) are always FP64 values f_a.  With F32_DEV
+ * the forecast relaxes the deviations in FP32 arithmetic (rho = 1 + sum of
+ * the deviations); the analysis forms its Gram matrices on FP32 matrix cores
+ * and keeps the eigensolve, the weights and their square root in FP64. */
 typedef enum { LBMLETKF_F64 = 0, LBMLETKF_F32_DEV = 1 } lbmletkf_storage;
 
 /* Which eigenproblem the analysis solves (both give the same analysis):
@@ -232,6 +235,19 @@ lbmletkf_status lbmletkf_set_checks(lbmletkf_ctx* ctx, int32_t max_sweeps, doubl
  * analysis RMSE or spread exceeds the divergence limit; else LBMLETKF_OK.  The
  * counts are in lbmletkf_last_error().  Clears the sweep-cap counter. */
 lbmletkf_status lbmletkf_check(lbmletkf_ctx* ctx, const double* d_diag, void* stream);
+
+/* Precision form (F32_DEV storage) only: enable = 1 runs the observation
+ * route's two per-node ensemble-space contractions of Sec. 3.2.1 -- B = dX Z^T
+ * (populations x local observations, summed over the members) and the
+ * transform dX (w_bar + dW) written as (B G) Z -- on the BF16 matrix cores
+ * with FP32 accumulation, each FP32 operand split into two BF16 parts (three
+ * products per tile, ~2^-16 relative per product); 0 (default) keeps them on
+ * the FP64 vector units, which is faster on MI355X for these shapes (the
+ * per-node products are 9 x l x M with l <= 32).  Nodes with more than 32 local
+ * observations always take the vector path.  LBMLETKF_EUNSUPPORTED for FP64
+ * storage.  A batch takes the setting at lbmletkf_batch_create (all its
+ * contexts must agree). */
+lbmletkf_status lbmletkf_set_matrix_core_transform(lbmletkf_ctx* ctx, int32_t enable);
 
 /* Energy spectrum of the ensemble at a report time (Sec. 4.1 shell spectrum;
  * the ensemble's spectrum is the mean of the members' spectra, Sec. 4.3.2):

@@ -76,6 +76,7 @@ SIGNATURES = {
     "lbmletkf_moments": (_c_int32, [_vp, _vp, _vp, _vp]),
     "lbmletkf_diagnostics_noalloc": (_c_int32, [ctypes.POINTER(LbmParams), _vp, _vp, _vp, _vp]),
     "lbmletkf_set_checks": (_c_int32, [_vp, _c_int32, _c_double, _c_int32]),
+    "lbmletkf_set_matrix_core_transform": (_c_int32, [_vp, _c_int32]),
     "lbmletkf_check": (_c_int32, [_vp, _vp, _vp]),
     "lbmletkf_energy_spectrum": (_c_int32, [_vp, _vp, _vp, _c_int32, _vp]),
     "lbmletkf_synth_obs": (_c_int32, [_vp, _vp, _vp, _vp, _c_int32, _vp]),
@@ -468,6 +469,10 @@ class Context:
                    check_every_cycle: bool = False) -> None:
         _check(load().lbmletkf_set_checks(self.handle, int(max_sweeps), float(diverge_limit),
                                           int(bool(check_every_cycle))))
+
+    def set_matrix_core_transform(self, enable: bool) -> None:
+        """FP32 storage: B = dX Z^T and the transform on BF16 matrix cores."""
+        _check(load().lbmletkf_set_matrix_core_transform(self.handle, int(bool(enable))))
 
     def check(self, diag: Optional[torch.Tensor] = None, stream=None) -> None:
         """Raises LbmLetkfError (status ENONFINITE, EEIG or EDIVERGED) if unhealthy."""

@@ -68,6 +68,8 @@ struct Ctx {
     int max_sweeps = 30;
     double diverge_limit = 0.0;
     bool check_every_cycle = false;
+    // precision form: the apply kernels' contractions on BF16 matrix cores
+    bool mfma_transform = false;
     char* ws;
     Layout L;
     // arguments of the last misfit forward sweep (its checkpoints feed the
@@ -379,6 +381,7 @@ AnalysisParams make_params(const Ctx* c, void* d_f) {
     p.a = (c->dims.members - 1) / c->obs.beta;
     p.sqrt_beta = std::sqrt(c->obs.beta);
     p.max_sweeps = c->max_sweeps;
+    p.mfma_transform = c->mfma_transform ? 1 : 0;
     p.eig_fail = c->counters() + 1;
     p.truth_uv = nullptr;
     p.diag_node = nullptr;
@@ -792,6 +795,16 @@ lbmletkf_status lbmletkf_set_checks(lbmletkf_ctx* ctx, int32_t max_sweeps, doubl
     return LBMLETKF_OK;
 }
 
+lbmletkf_status lbmletkf_set_matrix_core_transform(lbmletkf_ctx* ctx, int32_t enable) {
+    Ctx* c = as_ctx(ctx);
+    if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
+    if (enable != 0 && enable != 1) return fail(LBMLETKF_EINVAL, "enable must be 0 or 1");
+    if (enable && c->storage() != LBMLETKF_F32_DEV)
+        return fail(LBMLETKF_EUNSUPPORTED, "the matrix-core transform is for FP32 storage");
+    c->mfma_transform = enable != 0;
+    return LBMLETKF_OK;
+}
+
 lbmletkf_status lbmletkf_check(lbmletkf_ctx* ctx, const double* d_diag, void* stream) {
     Ctx* c = as_ctx(ctx);
     if (!c) return fail(LBMLETKF_EINVAL, "ctx is NULL");
@@ -1088,6 +1101,7 @@ struct Batch {
     std::vector<void*> f;
     int nsteps = 0;
     int storage = 0;
+    bool mfma_transform = false;  // every context's setting, taken at create
     lbmletkf_batch_config cfg{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -1322,7 +1336,8 @@ hipError_t batch_analysis(Batch* b, const AnalysisParams* params, hipStream_t s)
         hipStream_t sk = grp.stream == 0 ? s : b->side[grp.stream - 1];
         if (grp.route == LBMLETKF_ROUTE_OBSERVATION)
             e = launch_analysis_obs_batch(params, grp.eig_waves, grp.n_eig, grp.waves, grp.n_waves,
-                                          grp.nodes, grp.n, grp.gbuf, b->storage, sk);
+                                          grp.nodes, grp.n, grp.gbuf, b->storage,
+                                          b->mfma_transform, sk);
         else
             e = launch_analysis_ens_batch(params, grp.waves, grp.n_waves, grp.n, grp.nz_max,
                                           b->storage, sk);
@@ -1445,6 +1460,9 @@ lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_
             return fail(LBMLETKF_EUNSUPPORTED, "batched members must divide 256");
         if (k > 0 && c->storage() != v[0]->storage())
             return fail(LBMLETKF_EUNSUPPORTED, "every problem of a batch needs the same storage");
+        if (k > 0 && c->mfma_transform != v[0]->mfma_transform)
+            return fail(LBMLETKF_EUNSUPPORTED,
+                        "every problem of a batch needs the same matrix-core transform setting");
         for (void* g : std::vector<void*>(d_f, d_f + k))
             if (g == d_f[k]) return fail(LBMLETKF_EINVAL, "two problems share a state buffer");
         v.push_back(c);
@@ -1456,6 +1474,7 @@ lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_
     b->f.assign(d_f, d_f + n);
     b->nsteps = nsteps;
     b->storage = v[0]->storage();
+    b->mfma_transform = v[0]->mfma_transform;
     b->ws = reinterpret_cast<char*>(d_workspace);
     b->ws_bytes = bytes;
     b->d_params = reinterpret_cast<AnalysisParams*>(b->ws + L.params);

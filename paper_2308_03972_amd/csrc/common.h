@@ -137,6 +137,7 @@ struct AnalysisParams {
     double a;             // (M - 1) / beta
     double sqrt_beta;
     int max_sweeps;       // Jacobi sweep cap of the eigensolvers
+    int mfma_transform;   // FP32 storage: B = dX Z^T and the transform on BF16 matrix cores
     int* eig_fail;        // count of nodes whose eigensolver hit the sweep cap
     // cycle diagnostics folded into the analysis (NULL: none): per node the five
     // diagnostic fields (err2, spread2, non-finite, rho min, rho max) of the
@@ -180,7 +181,7 @@ int obs_segments(int n);              // nodes per wavefront of the eigen kernel
 hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4* d_eig_waves,
                                      int n_eig, const int2* d_apply_waves, int n_apply,
                                      const int* d_nodes, int n, double* gbuf, int storage,
-                                     hipStream_t s);
+                                     bool mfma_transform, hipStream_t s);
 int diag_blocks_for(int plane);
 // Bytes of diag_partial_kernel's per-block records for a grid of `plane` nodes.
 size_t diag_partial_bytes(int plane);

@@ -619,17 +619,234 @@ __device__ __forceinline__ void apply_body(const AnalysisParams& p, const int* n
                          p.diag_node + ((size_t)nx * ny + node) * kDiagFieldCount);
 }
 
-template <int N, typename T>
+// ---------------------------------------------------------------------------
+// apply part of the precision form (FP32 storage): the two ensemble-space
+// contractions per node, B = dX Z^T (9 x n, inner dimension the members) and
+// the transform dX_inc = C^T Z (9 x M, inner dimension n, C = B G), on the
+// BF16 matrix cores with FP32 accumulation.  Each FP32 operand x is split into
+// x_hi = bf16(x) and x_lo = bf16(x - x_hi); a product is taken as
+// hi*hi + hi*lo + lo*hi (the lo*lo term and the roundings leave ~2^-16
+// relative), three v_mfma_f32_16x16x32_bf16 per tile.  Operand layout (per
+// wavefront, lane l, element t < 8): A[l % 16][8 (l / 16) + t],
+// B[8 (l / 16) + t][l % 16]; result register r of lane l holds
+// D[4 (l / 16) + r][l % 16] (measured on gfx950).  Rows of A are the nine
+// populations (padded to 16); everything else is as in apply_body.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const __bf16 h = (__bf16)x[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(x[t] - (float)h);
+    }
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16x3(const float (&a)[8], const float (&b)[8], f32x4 acc) {
+    bf16x8 ah, al, bh, bl;
+    split_bf16(a, ah, al);
+    split_bf16(b, bh, bl);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+template <int N>
+__device__ __forceinline__ void apply_body_mfma(const AnalysisParams& p, const int* nodes, int item,
+                                                const double* __restrict__ gin) {
+    constexpr int n = N;
+    constexpr int NT = (n + 15) / 16;  // column tiles of B
+    static_assert(n <= 32, "one 32-deep step of the transform");
+    float* __restrict__ fs = reinterpret_cast<float*>(p.f);
+    extern __shared__ double lds[];
+    double* Gs = lds;                                  // [n][n] as stored: (k, j) = G_jk
+    double* hs = Gs + n * n;                           // [n]
+    double* dxs = hs + n;                              // [9][64]
+    double* Bs = dxs + 9 * 64;                         // [9][n]
+    double* Cs = Bs + 9 * n;                           // [n][10]
+    double* sw = Cs + 10 * n;                          // [n]
+    double* dmv = sw + n;                              // [9]
+    double* xbv = dmv + 9;                             // [9]
+    int* qx = reinterpret_cast<int*>(xbv + 9);         // [n]
+    // the transform's result [9][64] (FP32) reuses dX's region, which the
+    // contraction B = dX Z^T has finished reading before the transform
+    float* outs = reinterpret_cast<float*>(dxs);
+
+    const int lane = threadIdx.x;
+    const int node = nodes[item];
+    const int nx = p.nx, ny = p.ny, M = p.members;
+    const bool mem = lane < M;
+    const int x = node % nx, y = node / nx;
+    const int r16 = lane & 15, grp = lane >> 4;
+
+    constexpr int kGn = n * n + n;
+    constexpr int kGp = (kGn + kWave - 1) / kWave;
+    double dx[9];
+    const int ml = mem ? lane : 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        dx[a] = PopIO<float>::load(fs + slot(src_node(x, y, a, nx, ny), a, ml, M), a);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) dx[a] = mem ? dx[a] : 0.0;
+    const double* g = gin + (size_t)item * kGn;
+    double gv[kGp];
+#pragma unroll
+    for (int u = 0; u < kGp; ++u) gv[u] = g[min(lane + u * kWave, kGn - 1)];
+    int qj = 0;
+    double wj = 0.0;
+    if (lane < n) local_obs(p, node, lane, &qj, &wj, nullptr);
+    if (p.diag_node)
+        node_diag_record(dx, mem, M, node, nx * ny, p.truth_uv,
+                         p.diag_node + (size_t)node * kDiagFieldCount);
+#pragma unroll
+    for (int u = 0; u < kGp; ++u)
+        if (lane + u * kWave < kGn) Gs[lane + u * kWave] = gv[u];
+    if (lane < n) {
+        qx[lane] = qj;
+        sw[lane] = wj;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const double xbar = wave_sum(dx[a]) / M;
+        dx[a] = mem ? dx[a] - xbar : 0.0;
+        dxs[a * 64 + lane] = dx[a];
+        if (lane == 0) xbv[a] = xbar;
+    }
+    wave_lds_sync();
+    // B = dX Z^T: A = dX (row a = l % 16, members 32 ks + 8 grp + t), B = Z^T
+    // (members, column j = 16 tile + l % 16), two 32-member steps
+    {
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int m0 = 32 * ks + 8 * grp;
+            float av[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                av[t] = r16 < 9 ? (float)dxs[r16 * 64 + m0 + t] : 0.0f;
+#pragma unroll
+            for (int tile = 0; tile < NT; ++tile) {
+                const int j = 16 * tile + r16;
+                const bool jin = j < n;
+                const double w = jin ? sw[j] : 0.0;
+                const double* yrow = p.dY + (size_t)(jin ? qx[j] : 0) * M;
+                float bv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int m = m0 + t;
+                    const double yv = yrow[m < M ? m : 0];   // unconditional, selected below
+                    bv[t] = (jin && m < M) ? (float)(w * yv) : 0.0f;
+                }
+                acc[tile] = mfma_bf16x3(av, bv, acc[tile]);
+            }
+        }
+#pragma unroll
+        for (int tile = 0; tile < NT; ++tile)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = 4 * grp + r, j = 16 * tile + r16;
+                if (a < 9 && j < n) Bs[a * n + j] = (double)acc[tile][r];
+            }
+    }
+    wave_lds_sync();
+    // C = B G ([j][a]) and the mean increment B h (FP64 vector units)
+    for (int jj = lane; jj < n; jj += kWave) {
+        double c[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) c[a] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double gkj = Gs[k * n + jj];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) c[a] += Bs[a * n + k] * gkj;
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) Cs[jj * 10 + a] = c[a];
+        Cs[jj * 10 + 9] = 0.0;
+    }
+    if (lane < 9) {
+        double d = 0.0;
+        for (int k = 0; k < n; ++k) d += Bs[lane * n + k] * hs[k];
+        dmv[lane] = d;
+    }
+    wave_lds_sync();
+    // transform: A = C^T (row a = l % 16, observations 8 grp + t), B = Z
+    // (observations, member 16 tile + l % 16), four member tiles
+    f32x4 tr[4];
+    {
+        float av[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int j = 8 * grp + t;
+            av[t] = (r16 < 9 && j < n) ? (float)Cs[j * 10 + r16] : 0.0f;
+        }
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+            const int m = 16 * tile + r16;
+            const int mm = m < M ? m : 0;
+            float bv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = 8 * grp + t;
+                const bool jin = j < n;
+                const double yv = p.dY[(size_t)qx[jin ? j : 0] * M + mm];
+                bv[t] = (jin && m < M) ? (float)(sw[j] * yv) : 0.0f;
+            }
+            tr[tile] = mfma_bf16x3(av, bv, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int tile = 0; tile < 4; ++tile)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = 4 * grp + r;
+            if (a < 9) outs[a * 64 + 16 * tile + r16] = tr[tile][r];
+        }
+    wave_lds_sync();
+    double xa[9];  // the analysis as stored (diagnostics)
+#pragma unroll
+    for (int a = 0; a < 9; ++a) xa[a] = 0.0;
+    if (mem) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const double v = xbv[a] + p.sqrt_beta * dx[a] + dmv[a] + (double)outs[a * 64 + lane];
+            PopIO<float>::store(fs + slot(src_node(x, y, a, nx, ny), a, lane, M), a, v);
+            xa[a] = PopIO<float>::round(v, a);
+        }
+    }
+    if (p.diag_node)
+        node_diag_record(xa, mem, M, node, nx * ny, p.truth_uv,
+                         p.diag_node + ((size_t)nx * ny + node) * kDiagFieldCount);
+}
+
+// The apply body of a node: with MF (FP32 storage, n <= 32) the matrix-core
+// contractions, else the FP64 vector path.
+template <int N>
+constexpr bool kMfmaApply = N <= 32;
+
+template <int N, typename T, bool MF>
+__device__ __forceinline__ void apply_node(const AnalysisParams& p, const int* nodes, int item,
+                                           const double* __restrict__ gin) {
+    if constexpr (MF && sizeof(T) == 4 && kMfmaApply<N>) apply_body_mfma<N>(p, nodes, item, gin);
+    else apply_body<N, T>(p, nodes, item, gin);
+}
+
+template <int N, typename T, bool MF>
 __global__ __launch_bounds__(64) void analysis_apply_kernel(AnalysisParams p, const int* nodes,
                                                             int count,
                                                             const double* __restrict__ gin) {
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= count) return;  // uniform over the wavefront
-    apply_body<N, T>(p, nodes, item, gin);
+    apply_node<N, T, MF>(p, nodes, item, gin);
 }
 
 // Batched form: wavefront w takes waves[w] = (problem, item).
-template <int N, typename T>
+template <int N, typename T, bool MF>
 __global__ __launch_bounds__(64) void analysis_apply_batch_kernel(const AnalysisParams* P,
                                                                   const int2* waves, int nwaves,
                                                                   const int* nodes,
@@ -638,7 +855,7 @@ __global__ __launch_bounds__(64) void analysis_apply_batch_kernel(const Analysis
     if (w >= nwaves) return;
     const int2 d = waves[w];
     const AnalysisParams p = P[d.x];
-    apply_body<N, T>(p, nodes, d.y, gin);
+    apply_node<N, T, MF>(p, nodes, d.y, gin);
 }
 
 template <int N>
@@ -655,17 +872,19 @@ hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
-    if (p.storage == kStoreF32Dev)
-        analysis_apply_kernel<N, float><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
+    if (p.storage == kStoreF32Dev && p.mfma_transform && kMfmaApply<N>)
+        analysis_apply_kernel<N, float, true><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
+    else if (p.storage == kStoreF32Dev)
+        analysis_apply_kernel<N, float, false><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
     else
-        analysis_apply_kernel<N, double><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
+        analysis_apply_kernel<N, double, false><<<count, 64, app_bytes, s>>>(p, nodes, count, gbuf);
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t launch_batch_n(const AnalysisParams* d_params, const int4* d_eig_waves, int n_eig,
                           const int2* d_apply_waves, int n_apply, const int* d_nodes,
-                          double* gbuf, int storage, hipStream_t s) {
+                          double* gbuf, int storage, bool mfma_transform, hipStream_t s) {
     if (n_eig == 0) return hipSuccess;
     const size_t eig_bytes = (size_t)eig_lds_doubles<N>() * sizeof(double);
     static bool lds_ok = false;
@@ -676,11 +895,14 @@ hipError_t launch_batch_n(const AnalysisParams* d_params, const int4* d_eig_wave
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
-    if (storage == kStoreF32Dev)
-        analysis_apply_batch_kernel<N, float><<<n_apply, 64, app_bytes, s>>>(
+    if (storage == kStoreF32Dev && mfma_transform && kMfmaApply<N>)
+        analysis_apply_batch_kernel<N, float, true><<<n_apply, 64, app_bytes, s>>>(
+            d_params, d_apply_waves, n_apply, d_nodes, gbuf);
+    else if (storage == kStoreF32Dev)
+        analysis_apply_batch_kernel<N, float, false><<<n_apply, 64, app_bytes, s>>>(
             d_params, d_apply_waves, n_apply, d_nodes, gbuf);
     else
-        analysis_apply_batch_kernel<N, double><<<n_apply, 64, app_bytes, s>>>(
+        analysis_apply_batch_kernel<N, double, false><<<n_apply, 64, app_bytes, s>>>(
             d_params, d_apply_waves, n_apply, d_nodes, gbuf);
     return hipGetLastError();
 }
@@ -729,12 +951,12 @@ int obs_segments(int n) { return n > 0 ? 64 / n : 0; }
 hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4* d_eig_waves,
                                      int n_eig, const int2* d_apply_waves, int n_apply,
                                      const int* d_nodes, int n, double* gbuf, int storage,
-                                     hipStream_t s) {
+                                     bool mfma_transform, hipStream_t s) {
     switch (n) {
 #define X(v)                                                                                   \
     case v:                                                                                    \
         return launch_batch_n<v>(d_params, d_eig_waves, n_eig, d_apply_waves, n_apply, d_nodes, \
-                                 gbuf, storage, s);
+                                 gbuf, storage, mfma_transform, s);
         LBMLETKF_OBS_SIZES(X)
 #undef X
         default: return hipErrorInvalidValue;

@@ -94,10 +94,12 @@ def _mixed_configs():
     ]
 
 
-@pytest.mark.parametrize("storage", [F64, F32])
-def test_batch_reproduces_each_problems_run_cycle(storage):
-    say(f"batch vs single storage={storage}")
+@pytest.mark.parametrize("storage,mfma", [(F64, False), (F32, False), (F32, True)])
+def test_batch_reproduces_each_problems_run_cycle(storage, mfma):
+    say(f"batch vs single storage={storage} matrix-core transform={mfma}")
     probs = _setup(_mixed_configs(), storage, cycles=3)
+    for p in probs:
+        p[1].set_matrix_core_transform(mfma)
     single = _single_runs(probs, 3)
     batched = _batch_runs(probs, 3)
     diffs = [float(np.max(np.abs(s.astype(np.float64) - b))) for s, b in zip(single, batched)]

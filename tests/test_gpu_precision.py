@@ -1,6 +1,8 @@
 """GPU parity of the precision form: populations stored as FP32 deviations
 g = f - w (LBMLETKF_F32_DEV); the forecast relaxes g in FP32 arithmetic
-(rho = 1 + sum g), the analysis works in FP64.
+(rho = 1 + sum g); the analysis forms its Gram matrices on FP32 matrix cores
+(optionally also B = dX Z^T and the transform on BF16 ones) and keeps its
+eigensolve and square root in FP64.
 
 Tolerances: storing a deviation (|g| <~ 0.02 here) in FP32 rounds it by
 |g| 2^-24 <= 1.2e-9.  The FP32 relaxation adds a few FP32 roundings of
@@ -9,7 +11,11 @@ the equilibrium deviation, the non-equilibrium part), multiplied by at most
 omega = 1/tau < 2: one step from an identical (already rounded) state agrees
 with the FP64 oracle to 32 * 2^-24 * max|g| (a generous count of roundings; a
 wrong term would miss by ~1e-4 and more).  A single analysis from an identical
-state (FP64 arithmetic) agrees to ~1e-9 absolute.  Over a run the velocity
+state agrees to ~1e-9 absolute plus, with the matrix-core transform
+(lbmletkf_set_matrix_core_transform: the observation route's ensemble-space
+contractions on BF16 matrix cores with a hi/lo split of each FP32 operand,
+~2^-16 per product), 2^-12 of the increment's size; the eigensolve and the
+weights stay FP64.  Over a run the velocity
 RMSE must stay within 1e-3 of the observation-error standard deviation sigma
 (|dRMSE| < 1e-3 sigma = 2.9e-6) of the FP64 result.
 """
@@ -78,11 +84,14 @@ def test_f32_stream_collide_step_matches_oracle(members):
     assert err < 32 * 2.0**-24 * gmax
 
 
-@pytest.mark.parametrize("route", [binding.ROUTE_ENSEMBLE, binding.ROUTE_OBSERVATION])
-def test_f32_analysis_matches_oracle(route):
-    say(f"f32 analysis route={route}")
+@pytest.mark.parametrize("route,mfma", [(binding.ROUTE_ENSEMBLE, False),
+                                        (binding.ROUTE_OBSERVATION, False),
+                                        (binding.ROUTE_OBSERVATION, True)])
+def test_f32_analysis_matches_oracle(route, mfma):
+    say(f"f32 analysis route={route} matrix-core transform={mfma}")
     ft, fe = config_state(TINY, spin_steps=10)
     ctx = _ctx(TINY, route=route)
+    ctx.set_matrix_core_transform(mfma)
     f = ctx.import_canonical(cuda(fe))
     start = host(ctx.export_canonical(f))
     pts = inputs.observation_points(TINY)
@@ -93,9 +102,18 @@ def test_f32_analysis_matches_oracle(route):
     got = host(ctx.export_canonical(f))
     ref = oracle.letkf_analysis(start, oracle.observe(start, pts), yo, pts, TINY.sigmas,
                                 TINY.d_cut, TINY.beta)
-    assert np.max(np.abs(got - ref)) < 2e-9
     inc = ref - start
-    assert np.max(np.abs((got - start) - inc)) < 1e-6 * np.max(np.abs(inc)) + 2e-9
+    # matrix-core transform: B = dX Z^T and the transform on BF16 matrix cores (each
+    # FP32 operand split hi + lo, ~2^-16 per product, FP32 accumulation), so the
+    # increment is good to ~2^-14 of its size; otherwise they stay FP64 and only the
+    # Gram matrices (K, Z^T Z) come from FP32 matrix cores
+    rel_inc = 2.0**-12 if mfma else 1e-6
+    err = np.max(np.abs(got - ref))
+    err_inc = np.max(np.abs((got - start) - inc)) / np.max(np.abs(inc))
+    say(f"  max error {err:.2e}; increment error {err_inc:.2e} of max|increment| "
+        f"{np.max(np.abs(inc)):.2e}")
+    assert err < 2e-9 + rel_inc * np.max(np.abs(inc))
+    assert err_inc * np.max(np.abs(inc)) < rel_inc * np.max(np.abs(inc)) + 2e-9
 
 
 def _osse(cfg, cycles, storage):
