@@ -402,8 +402,11 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
     }
 }
 
-// Up to N = 18 the eigensolver fits in 168 VGPRs (three wavefronts per SIMD)
-// without spilling; larger N keep the compiler's choice.
+// Split rows above N = 32.  At N = 32 itself one wavefront holding two nodes
+// with whole rows beats one node with half rows in a wavefront (measured 103
+// against 134 ns per node at 64 members).  Up to N = 18 the eigensolver fits
+// in 168 VGPRs (three wavefronts per SIMD) without spilling; larger N keep the
+// compiler's choice.
 template <int N>
 constexpr bool kSplitRows = N > 32;
 
