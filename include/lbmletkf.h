@@ -338,8 +338,9 @@ lbmletkf_status lbmletkf_misfit_backward(lbmletkf_ctx* ctx, const void* d_f0, do
  * network; members >= 2 must divide 256 and every context must have the same
  * storage) to their state buffers d_f[k] and advances all of them one cycle
  * (Sec. 3 workflow (ii)-(iv), as run_cycle without diagnostics) per call:
- *   - the forecast of all problems is one persistent launch per step over the
- *     concatenated (problem, node tile) list;
+ *   - the forecast of all problems is one launch per step over the
+ *     concatenated (problem, node tile) list, or one launch per pair of steps
+ *     over the concatenated (problem, tile, member group) blocks;
  *   - H and the observation statistics run per problem;
  *   - the analyses are grouped across problems by eigenproblem size (one
  *     eigen + one apply launch, or one ensemble-route launch, per size),
@@ -360,14 +361,19 @@ typedef struct {
                                    members per thread with FP32 storage and even M, else 1 */
     int32_t bucket_granularity; /* eigenproblem sizes rounded up to multiples of 2, 4 or 8 */
     int32_t use_graph;          /* 1: capture the cycle once as a hipGraph and replay it */
+    int32_t steps_per_launch;   /* 1: the launch above per step; 2: pairs of steps in one launch
+                                   over every problem's (6 x 6 tile, 16-member group) blocks, the
+                                   first step's results kept on chip (needs 16 | members in every
+                                   problem; the same bits as single steps) */
 } lbmletkf_batch_config;
 
 lbmletkf_status lbmletkf_batch_workspace_bytes(lbmletkf_ctx* const* ctxs, int32_t n, size_t* bytes);
 
 /* Create a batch of n contexts with states d_f[k] (device, storage layout) and
  * nsteps forecast steps per cycle.  ctxs and d_f are host arrays of n pointers.
- * cfg may be NULL: {one block per tile, 4 tile rows, granularity 2, graph}.  Waits for
- * its setup copies and, with use_graph, captures the cycle. */
+ * cfg may be NULL: {one block per tile, 4 tile rows, granularity 2, graph, two steps per
+ * launch where every problem allows it, else one}.  Waits for its setup copies and,
+ * with use_graph, captures the cycle. */
 lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_f, int32_t n,
                                       int32_t nsteps, const lbmletkf_batch_config* cfg,
                                       void* d_workspace, size_t bytes, void* stream,
@@ -385,7 +391,8 @@ lbmletkf_status lbmletkf_batch_set_config(lbmletkf_batch* batch, const lbmletkf_
                                           void* stream);
 
 /* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048, 0}) x
- * (tile_rows in {1, 2, 4, 8}) forecast step and every bucket granularity
+ * (tile_rows in {1, 2, 4, 8}) forecast step, the two-step launch (per step, when
+ * every problem allows it) and every bucket granularity
  * {2, 4, 8} of the analysis (reps timed runs each, HIP events), then applies
  * the fastest with use_graph = 1.  Runs on the contexts' ping-pong partner
  * buffers: the bound states are not modified.  Outputs (any may be NULL): the

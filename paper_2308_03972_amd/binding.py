@@ -46,7 +46,8 @@ class ObsParams(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("forecast_blocks", _c_int32), ("tile_rows", _c_int32),
-                ("bucket_granularity", _c_int32), ("use_graph", _c_int32)]
+                ("bucket_granularity", _c_int32), ("use_graph", _c_int32),
+                ("steps_per_launch", _c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -543,7 +544,7 @@ class Batch:
         aligned = (self.workspace.data_ptr() + 255) // 256 * 256
         cfg = None
         if config is not None:
-            cfg = BatchConfig(**{k: int(v) for k, v in config.items()})
+            cfg = BatchConfig(**{"steps_per_launch": 1, **{k: int(v) for k, v in config.items()}})
         h = _vp()
         _check(lib.lbmletkf_batch_create(self._ctxs, self._fs, n, self.nsteps,
                                          ctypes.byref(cfg) if cfg is not None else None, aligned,
@@ -566,7 +567,7 @@ class Batch:
         return cfg.as_dict()
 
     def set_config(self, config: dict, stream=None) -> None:
-        cfg = BatchConfig(**{k: int(v) for k, v in config.items()})
+        cfg = BatchConfig(**{"steps_per_launch": 1, **{k: int(v) for k, v in config.items()}})
         _check(load().lbmletkf_batch_set_config(self.handle, ctypes.byref(cfg), _stream(stream)))
 
     def tune(self, reps: int = 3, stream=None) -> Tuple[dict, float, float]:

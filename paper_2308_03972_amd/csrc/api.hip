@@ -1114,6 +1114,7 @@ struct Batch {
     size_t gcap = 0;
     std::vector<BatchGroup> groups;
     int ntiles = 0;
+    int nblocks2 = 0;  // blocks of a batched two-step launch
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
     hipStream_t cap = nullptr;
@@ -1180,7 +1181,7 @@ void batch_release(Batch* b) {
 lbmletkf_status batch_tasks(Batch* b, hipStream_t s) {
     const int n = (int)b->ctx.size();
     std::vector<LbmTask> t(3 * n);
-    int tile0 = 0;
+    int tile0 = 0, block0 = 0;
     for (int k = 0; k < n; ++k) {
         const Ctx* c = b->ctx[k];
         const int M = c->dims.members;
@@ -1199,13 +1200,17 @@ lbmletkf_status batch_tasks(Batch* b, hipStream_t s) {
             x.members = M;
             x.tile_nodes = tile_nodes;
             x.tile0 = tile0;
+            x.block0 = block0;
             x.tau0 = c->lbm.tau0;
             x.smag = 18.0 * std::sqrt(2.0) * c->lbm.cs * c->lbm.cs;
             x.mu = c->lbm.mu;
         }
         tile0 += (plane + tile_nodes - 1) / tile_nodes;
+        if (two_step_supported(c->dims, c->storage()))
+            block0 += two_step_blocks(c->dims, c->storage());
     }
     b->ntiles = tile0;
+    b->nblocks2 = block0;
     hipError_t e = hipMemcpyAsync(b->d_tasks[0], t.data(), t.size() * sizeof(LbmTask),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1372,17 +1377,41 @@ int forecast_grid(const Batch* b) {
     return b->cfg.forecast_blocks > 0 ? b->cfg.forecast_blocks : std::max(b->ntiles, 1);
 }
 
-// One whole cycle of every problem on stream s.
-hipError_t batch_issue_cycle(Batch* b, hipStream_t s) {
+// Whether every problem of the batch can take two steps per launch.
+bool batch_two_step_ok(const Batch* b) {
+    for (const Ctx* c : b->ctx)
+        if (!two_step_supported(c->dims, c->storage())) return false;
+    return true;
+}
+
+// The forecast of every problem: nsteps steps in launches of one or two steps
+// (config), alternating between the bound states and their partners; an odd
+// number of launches leaves the result in the partners, which are copied back.
+hipError_t batch_forecast(Batch* b, hipStream_t s) {
     hipError_t e = hipSuccess;
     const int n = (int)b->ctx.size();
-    for (int step = 0; step < b->nsteps && e == hipSuccess; ++step)
-        e = launch_stream_collide_batch(b->d_tasks[step & 1], n, b->ntiles,
-                                        forecast_grid(b), b->storage, s);
-    if (b->nsteps & 1)
+    const bool two = b->cfg.steps_per_launch == 2;
+    int launches = 0;
+    for (int step = 0; step < b->nsteps && e == hipSuccess; ++launches) {
+        const LbmTask* tasks = b->d_tasks[launches & 1];
+        if (two && b->nsteps - step >= 2) {
+            e = launch_stream_collide2_batch(tasks, n, b->nblocks2, b->storage, s);
+            step += 2;
+        } else {
+            e = launch_stream_collide_batch(tasks, n, b->ntiles, forecast_grid(b), b->storage, s);
+            step += 1;
+        }
+    }
+    if (launches & 1)
         for (int k = 0; k < n && e == hipSuccess; ++k)
             e = hipMemcpyAsync(b->f[k], b->ctx[k]->fbuf(), b->ctx[k]->state_bytes(),
                                hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+// One whole cycle of every problem on stream s.
+hipError_t batch_issue_cycle(Batch* b, hipStream_t s) {
+    hipError_t e = batch_forecast(b, s);
     if (e == hipSuccess) e = batch_observe(b, false, s);
     if (e == hipSuccess) e = batch_analysis(b, b->d_params, s);
     return e;
@@ -1411,12 +1440,16 @@ lbmletkf_status batch_check_config(const lbmletkf_batch_config* cfg) {
     if (cfg->bucket_granularity != 2 && cfg->bucket_granularity != 4 &&
         cfg->bucket_granularity != 8)
         return fail(LBMLETKF_EINVAL, "bucket_granularity must be 2, 4 or 8");
+    if (cfg->steps_per_launch != 1 && cfg->steps_per_launch != 2)
+        return fail(LBMLETKF_EINVAL, "steps_per_launch must be 1 or 2");
     return LBMLETKF_OK;
 }
 
 lbmletkf_status batch_apply_config(Batch* b, const lbmletkf_batch_config* cfg, hipStream_t s) {
     lbmletkf_status st = batch_check_config(cfg);
     if (st) return st;
+    if (cfg->steps_per_launch == 2 && !batch_two_step_ok(b))
+        return fail(LBMLETKF_EUNSUPPORTED, "two steps per launch need 16 | members in every problem");
     b->cfg = *cfg;
     if ((st = batch_tasks(b, s))) return st;
     if ((st = batch_groups(b, s))) return st;
@@ -1447,7 +1480,7 @@ lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_
     if (nsteps < 1) return fail(LBMLETKF_EINVAL, "nsteps must be >= 1");
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
         return fail(LBMLETKF_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-    lbmletkf_batch_config c0{0, 4, 2, 1};
+    lbmletkf_batch_config c0{0, 4, 2, 1, 1};
     const lbmletkf_batch_config* use = cfg ? cfg : &c0;
     lbmletkf_status st = batch_check_config(use);
     if (st) return st;
@@ -1511,7 +1544,9 @@ lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_
         delete b;
         return hip_fail(e, "lbmletkf_batch_create");
     }
-    if ((st = batch_apply_config(b, use, s))) {
+    lbmletkf_batch_config first = *use;
+    if (!cfg && batch_two_step_ok(b)) first.steps_per_launch = 2;  // default: two where possible
+    if ((st = batch_apply_config(b, &first, s))) {
         batch_release(b);
         delete b;
         return st;
@@ -1601,7 +1636,21 @@ lbmletkf_status lbmletkf_batch_tune(lbmletkf_batch* batch, int32_t reps, lbmletk
                 best_f = ms;
                 best_cfg.forecast_blocks = bl;
                 best_cfg.tile_rows = tr;
+                best_cfg.steps_per_launch = 1;
             }
+        }
+    }
+    // two steps per launch over the concatenated (problem, tile, member group)
+    // blocks, priced per step
+    if (e == hipSuccess && !st && batch_two_step_ok(b)) {
+        double ms = 0.0;
+        e = timed([&]() {
+            return launch_stream_collide2_batch(b->d_tasks[2], (int)b->ctx.size(), b->nblocks2,
+                                                b->storage, s);
+        }, &ms);
+        if (e == hipSuccess && ms / 2 < best_f) {
+            best_f = ms / 2;
+            best_cfg.steps_per_launch = 2;
         }
     }
     // analysis: bucket granularity, on copies of the states in the partner buffers

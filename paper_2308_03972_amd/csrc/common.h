@@ -101,11 +101,20 @@ struct LbmTask {
     int nx, ny, members;  // members divides 256
     int tile_nodes;       // nodes per tile (a multiple of 256 / members)
     int tile0;            // first tile of this problem in the concatenated list
+    int block0;           // first block of this problem in a batched two-step launch
     double tau0, smag, mu;
 };
 // All problems' steps in one persistent launch of `blocks` blocks over `ntiles` tiles.
 hipError_t launch_stream_collide_batch(const LbmTask* d_tasks, int ntasks, int ntiles, int blocks,
                                        int storage, hipStream_t s);
+// Blocks of one problem's two-step launch in a batch (tiles x member groups of
+// 16, or of 32 for FP32 storage with 32 | members; needs 16 | members), and two
+// steps of all problems in one launch over the concatenated block list
+// (nblocks = sum of two_step_blocks); the same arithmetic and rounding as the
+// single-problem two-step launch.
+int two_step_blocks(LbmDims d, int storage);
+hipError_t launch_stream_collide2_batch(const LbmTask* d_tasks, int ntasks, int nblocks,
+                                        int storage, hipStream_t s);
 hipError_t launch_import(const double* canon, void* f, LbmDims d, int storage, hipStream_t s);
 hipError_t launch_export(const void* f, double* canon, LbmDims d, int storage, hipStream_t s);
 hipError_t launch_init_equilibrium(const double* rho, const double* uv, void* f, LbmDims d,

@@ -250,14 +250,17 @@ constexpr int kTwoR = kTwoT + 2;
 
 __host__ __device__ constexpr int two_step_lds_doubles() { return kTwoR * kTwoR * 9 * kTwoMG; }
 
-template <typename T>
-__global__ __launch_bounds__(kTwoMG * kTwoR * kTwoR) void stream_collide2_kernel(
-    const T* __restrict__ fin, T* __restrict__ fout, const double* __restrict__ force, int nx,
-    int ny, int members, double tau0, double smag, double mu) {
+// Block b of a two-step launch over one problem (FP64 storage): member group
+// b % (members / kTwoMG) of tile b / (members / kTwoMG).
+__device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
+                                              double* __restrict__ fout,
+                                              const double* __restrict__ force, int nx, int ny,
+                                              int members, double tau0, double smag, double mu,
+                                              int b) {
     extern __shared__ double mid[];  // [kTwoR * kTwoR][9][kTwoMG]
+    using T = double;
     const int groups = members / kTwoMG;
     const int tiles_x = (nx + kTwoT - 1) / kTwoT;
-    const int b = blockIdx.x;
     const int mg = b % groups, tile = b / groups;
     const int x0 = (tile % tiles_x) * kTwoT, y0 = (tile / tiles_x) * kTwoT;
     const int m = mg * kTwoMG + threadIdx.x;
@@ -290,6 +293,114 @@ __global__ __launch_bounds__(kTwoMG * kTwoR * kTwoR) void stream_collide2_kernel
     collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
     for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
+}
+
+__global__ __launch_bounds__(kTwoMG * kTwoR * kTwoR) void stream_collide2_kernel(
+    const double* __restrict__ fin, double* __restrict__ fout, const double* __restrict__ force,
+    int nx, int ny, int members, double tau0, double smag, double mu) {
+    two_step_body(fin, fout, force, nx, ny, members, tau0, smag, mu, blockIdx.x);
+}
+
+// The two-step kernel for FP32 storage: the FP32 relaxation on deviations
+// (collide_node_dev), MG members per block as MG / 2 threads of two adjacent
+// members each (8-byte accesses, as in the single step), the intermediate
+// deviations kept in LDS as FP32 -- exactly the values a single step would
+// store -- so that a launch equals two single-step launches bit for bit.
+// Block b of a two-step launch over one problem (FP32 storage): member group
+// b % (members / gsize) of tile b / (members / gsize), gsize <= MG members per
+// group (threads with 2 threadIdx.x >= gsize idle: a batch runs 16-member
+// problems in 32-member blocks).
+template <int MG>
+__device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
+                                                  float* __restrict__ fout,
+                                                  const double* __restrict__ force, int nx, int ny,
+                                                  int members, float tau0, float smag, float mu,
+                                                  int b, int gsize) {
+    extern __shared__ float mids[];  // [kTwoR * kTwoR][9][MG]
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const int groups = members / gsize;
+    const int tiles_x = (nx + kTwoT - 1) / kTwoT;
+    const int mg = b % groups, tile = b / groups;
+    const int x0 = (tile % tiles_x) * kTwoT, y0 = (tile / tiles_x) * kTwoT;
+    const int mp = 2 * threadIdx.x;          // first member of the pair within the group
+    const bool on = mp < gsize;
+    const int m = mg * gsize + (on ? mp : 0);
+    const int r = threadIdx.y, rx = r % kTwoR, ry = r / kTwoR;
+    const int gx = (x0 - 1 + rx + nx) % nx, gy = (y0 - 1 + ry + ny) % ny;
+    const int plane = nx * ny;
+    const int node = gy * nx + gx;
+    float fx = 0.0f, fy = 0.0f;
+    if (force) {
+        fx = (float)force[node];
+        fy = (float)force[plane + node];
+    }
+    float g0[9], g1[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const f2 v = __builtin_nontemporal_load(
+            reinterpret_cast<const f2*>(fin + slot(src_node(gx, gy, a, nx, ny), a, m, members)));
+        g0[a] = v.x;
+        g1[a] = v.y;
+    }
+    collide_node_dev(g0, tau0, smag, fx, fy, mu);
+    collide_node_dev(g1, tau0, smag, fx, fy, mu);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        f2 v;
+        v.x = g0[a];
+        v.y = g1[a];
+        *reinterpret_cast<f2*>(mids + (r * 9 + a) * MG + mp) = v;
+    }
+    __syncthreads();
+    const int ix = rx - 1, iy = ry - 1;
+    if (!on) return;
+    if (ix < 0 || ix >= kTwoT || iy < 0 || iy >= kTwoT || x0 + ix >= nx || y0 + iy >= ny) return;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const f2 v = *reinterpret_cast<const f2*>(
+            mids + (((ry - cy_of(a)) * kTwoR + rx - cx_of(a)) * 9 + a) * MG + mp);
+        g0[a] = v.x;
+        g1[a] = v.y;
+    }
+    collide_node_dev(g0, tau0, smag, fx, fy, mu);
+    collide_node_dev(g1, tau0, smag, fx, fy, mu);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        f2 v;
+        v.x = g0[a];
+        v.y = g1[a];
+        __builtin_nontemporal_store(v, reinterpret_cast<f2*>(fout + slot(node, a, m, members)));
+    }
+}
+
+template <int MG>
+__global__ __launch_bounds__(MG / 2 * kTwoR * kTwoR) void stream_collide2_dev_kernel(
+    const float* __restrict__ fin, float* __restrict__ fout, const double* __restrict__ force,
+    int nx, int ny, int members, float tau0, float smag, float mu) {
+    two_step_dev_body<MG>(fin, fout, force, nx, ny, members, tau0, smag, mu, blockIdx.x, MG);
+}
+
+// Two steps of many problems in one launch: block b belongs to the task k
+// with block0_k <= b < block0_{k+1} (a problem's blocks are its tiles x member
+// groups: 16 members for FP64 storage, 32 -- or 16 for a 16-member problem --
+// for FP32 storage), and runs that problem's two-step block b - block0_k.
+constexpr int kTwoMG32 = 32;  // members per block of the FP32 batched launch
+
+template <typename T>
+__global__ __launch_bounds__((sizeof(T) == 8 ? kTwoMG : kTwoMG32 / 2) * kTwoR * kTwoR) void
+stream_collide2_batch_kernel(const LbmTask* __restrict__ tasks, int ntasks) {
+    const int b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < ntasks && tasks[k + 1].block0 <= b) ++k;
+    const LbmTask& tk = tasks[k];
+    if constexpr (sizeof(T) == 8)
+        two_step_body(static_cast<const double*>(tk.fin), static_cast<double*>(tk.fout), tk.force,
+                      tk.nx, tk.ny, tk.members, tk.tau0, tk.smag, tk.mu, b - tk.block0);
+    else
+        two_step_dev_body<kTwoMG32>(static_cast<const float*>(tk.fin),
+                                    static_cast<float*>(tk.fout), tk.force, tk.nx, tk.ny,
+                                    tk.members, (float)tk.tau0, (float)tk.smag, (float)tk.mu,
+                                    b - tk.block0, tk.members % kTwoMG32 == 0 ? kTwoMG32 : kTwoMG);
 }
 
 // storage slot (node (x, y), a, m) <- canonical [m][a][y + c_ay][x + c_ax]
@@ -405,26 +516,52 @@ hipError_t launch_stream_collide(const void* fin, void* fout, const double* forc
 }
 
 bool two_step_supported(LbmDims d, int storage) {
-    // FP32 storage keeps one step per launch (its FP32 relaxation on two members
-    // per thread); the tiled two-step kernel is the FP64 form's
-    return storage == kStoreF64 && d.members % kTwoMG == 0;
+    // FP64: blocks of 16 members; FP32 deviations: 32 (or 16) members as pairs
+    return d.members % kTwoMG == 0;
 }
 
 hipError_t launch_stream_collide2(const void* fin, void* fout, const double* force, LbmDims d,
                                   double tau0, double cs, double mu, int storage, hipStream_t s) {
     if (!two_step_supported(d, storage)) return hipErrorInvalidValue;
     const int tiles = ((d.nx + kTwoT - 1) / kTwoT) * ((d.ny + kTwoT - 1) / kTwoT);
+    const double smag = 18.0 * sqrt(2.0) * cs * cs;
+    hipError_t e = hipSuccess;
+    if (storage == kStoreF32Dev) {
+        static bool attr32 = false, attr16 = false;
+        if (d.members % 32 == 0) {
+            const size_t bytes = (size_t)kTwoR * kTwoR * 9 * 32 * sizeof(float);
+            if (!attr32)
+                e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_dev_kernel<32>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+            attr32 = true;
+            stream_collide2_dev_kernel<32><<<tiles * (d.members / 32), dim3(16, kTwoR * kTwoR),
+                                             bytes, s>>>((const float*)fin, (float*)fout, force,
+                                                         d.nx, d.ny, d.members, (float)tau0,
+                                                         (float)smag, (float)mu);
+        } else {
+            const size_t bytes = (size_t)kTwoR * kTwoR * 9 * 16 * sizeof(float);
+            if (!attr16)
+                e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_dev_kernel<16>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+            attr16 = true;
+            stream_collide2_dev_kernel<16><<<tiles * (d.members / 16), dim3(8, kTwoR * kTwoR),
+                                             bytes, s>>>((const float*)fin, (float*)fout, force,
+                                                         d.nx, d.ny, d.members, (float)tau0,
+                                                         (float)smag, (float)mu);
+        }
+        return hipGetLastError();
+    }
     const dim3 grid(tiles * (d.members / kTwoMG)), block(kTwoMG, kTwoR * kTwoR);
     const size_t bytes = (size_t)two_step_lds_doubles() * sizeof(double);
-    const double smag = 18.0 * sqrt(2.0) * cs * cs;
     static bool attr = false;
-    hipError_t e = hipSuccess;
     if (!attr)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel<double>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr = true;
-    stream_collide2_kernel<double><<<grid, block, bytes, s>>>(
+    stream_collide2_kernel<<<grid, block, bytes, s>>>(
         (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
     return hipGetLastError();
 }
@@ -435,6 +572,37 @@ hipError_t launch_stream_collide_batch(const LbmTask* d_tasks, int ntasks, int n
         stream_collide_batch_kernel<float><<<blocks, kBlock, 0, s>>>(d_tasks, ntasks, ntiles);
     else
         stream_collide_batch_kernel<double><<<blocks, kBlock, 0, s>>>(d_tasks, ntasks, ntiles);
+    return hipGetLastError();
+}
+
+int two_step_blocks(LbmDims d, int storage) {
+    const int g = (storage == kStoreF32Dev && d.members % kTwoMG32 == 0) ? kTwoMG32 : kTwoMG;
+    return ((d.nx + kTwoT - 1) / kTwoT) * ((d.ny + kTwoT - 1) / kTwoT) * (d.members / g);
+}
+
+hipError_t launch_stream_collide2_batch(const LbmTask* d_tasks, int ntasks, int nblocks,
+                                        int storage, hipStream_t s) {
+    static bool attr64 = false, attr32 = false;
+    hipError_t e = hipSuccess;
+    if (storage == kStoreF32Dev) {
+        const size_t bytes = (size_t)kTwoR * kTwoR * 9 * kTwoMG32 * sizeof(float);
+        if (!attr32)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_batch_kernel<float>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr32 = true;
+        stream_collide2_batch_kernel<float><<<nblocks, dim3(kTwoMG32 / 2, kTwoR * kTwoR), bytes,
+                                              s>>>(d_tasks, ntasks);
+    } else {
+        const size_t bytes = (size_t)two_step_lds_doubles() * sizeof(double);
+        if (!attr64)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(stream_collide2_batch_kernel<double>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr64 = true;
+        stream_collide2_batch_kernel<double><<<nblocks, dim3(kTwoMG, kTwoR * kTwoR), bytes, s>>>(
+            d_tasks, ntasks);
+    }
     return hipGetLastError();
 }
 

@@ -108,6 +108,28 @@ def test_batch_reproduces_each_problems_run_cycle(storage, mfma):
         assert np.array_equal(s, b)
 
 
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_batch_two_step_launches_reproduce_run_cycle(storage):
+    """Problems with 16 | M: the batch's two-step launch over every problem's
+    (tile, member group) blocks, with an odd step count (the last step single),
+    against each problem's own run_cycle, bit for bit, graph and eager."""
+    say(f"batch two-step launches storage={storage}")
+    base = inputs.CONFIGS["tiny"]
+    cfgs = [base.replace(name="t1", n=32, members=16, steps_per_cycle=7, seed=21),
+            base.replace(name="t2", n=37, members=32, obs_side=4, loc_r=3.0, steps_per_cycle=7,
+                         seed=22),
+            base.replace(name="t3", n=26, members=64, obs_side=4, loc_r=5.0, steps_per_cycle=7,
+                         seed=23)]
+    probs = _setup(cfgs, storage, cycles=3)
+    single = _single_runs(probs, 3)
+    for graph in (1, 0):
+        batched = _batch_runs(probs, 3, config=dict(forecast_blocks=0, tile_rows=2,
+                                                    bucket_granularity=2, use_graph=graph,
+                                                    steps_per_launch=2))
+        for s_, b_ in zip(single, batched):
+            assert np.array_equal(s_, b_)
+
+
 def test_batch_graph_replays_match_eager_launches():
     """Three cycles replayed from the captured graph against the same cycles
     issued launch by launch, compared after every cycle."""
@@ -215,4 +237,15 @@ def test_batch_argument_errors():
     f6 = c6.init_equilibrium(m5[:1].contiguous())
     with pytest.raises(binding.LbmLetkfError) as e:      # one member: no analysis
         binding.Batch([c5, c6], [c5.init_equilibrium(m5), f6], 10)
+    assert e.value.status == -1
+    # two steps per launch need 16 | members (tiny has 8); the count must be 1 or 2
+    with pytest.raises(binding.LbmLetkfError) as e:
+        binding.Batch([c1], [f1], 10, config=dict(forecast_blocks=0, tile_rows=2,
+                                                  bucket_granularity=2, use_graph=0,
+                                                  steps_per_launch=2))
+    assert e.value.status == -8
+    with pytest.raises(binding.LbmLetkfError) as e:
+        binding.Batch([c1], [f1], 10, config=dict(forecast_blocks=0, tile_rows=2,
+                                                  bucket_granularity=2, use_graph=0,
+                                                  steps_per_launch=3))
     assert e.value.status == -1
