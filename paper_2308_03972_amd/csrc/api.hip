@@ -869,16 +869,29 @@ struct Sweep {
     void* seg(int j) const { return w + L.seg + (size_t)(j - 1) * sb; }
 };
 
-// Steps 1 .. last of the segment that starts at checkpoint t - 1; step
-// `steps` (if last == steps) lands in checkpoint t.
+// Steps 1 .. last of the segment that starts at checkpoint t - 1, every state
+// kept; step `steps` (if last == steps) lands in checkpoint t.  Pairs of steps
+// run in one launch that also writes the pair's first state, where the
+// ensemble allows it (the same bits as single steps).
 lbmletkf_status segment_steps(Ctx* c, const Sweep& sw, int t, int steps, int last, double cs,
                               hipStream_t s) {
-    for (int j = 1; j <= last; ++j) {
+    const bool two = two_step_supported(c->dims, c->storage());
+    for (int j = 1; j <= last;) {
         const void* in = j == 1 ? sw.ckpt(t - 1) : sw.seg(j - 1);
-        void* out = j == steps ? sw.ckpt_mut(t) : sw.seg(j);
-        StageTimer tm(c, kStageCollide, s);
-        hipError_t e = launch_stream_collide(in, out, c->force(), c->dims, c->lbm.tau0, cs,
-                                             c->lbm.mu, c->storage(), s);
+        hipError_t e;
+        if (two && j + 1 <= last) {
+            void* out = j + 1 == steps ? sw.ckpt_mut(t) : sw.seg(j + 1);
+            StageTimer tm(c, kStageCollide, s, kPerLaunch, 2);
+            e = launch_stream_collide2(in, out, c->force(), c->dims, c->lbm.tau0, cs, c->lbm.mu,
+                                       c->storage(), s, sw.seg(j));
+            j += 2;
+        } else {
+            void* out = j == steps ? sw.ckpt_mut(t) : sw.seg(j);
+            StageTimer tm(c, kStageCollide, s);
+            e = launch_stream_collide(in, out, c->force(), c->dims, c->lbm.tau0, cs, c->lbm.mu,
+                                      c->storage(), s);
+            j += 1;
+        }
         if (e != hipSuccess) return hip_fail(e, "stream_collide");
     }
     return LBMLETKF_OK;

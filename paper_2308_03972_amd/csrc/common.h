@@ -88,10 +88,13 @@ hipError_t launch_stream_collide(const void* fin, void* fout, const double* forc
                                  double tau0, double cs, double mu, int storage, hipStream_t s);
 // Two such steps in one launch (spatial tiles with a recomputed one-node ring,
 // the intermediate state in LDS); needs two_step_supported(d).  Same
-// arithmetic and rounding as two launches of launch_stream_collide.
+// arithmetic and rounding as two launches of launch_stream_collide; with fmid
+// != NULL the intermediate state is written there too (the first launch's
+// output).
 bool two_step_supported(LbmDims d, int storage);
 hipError_t launch_stream_collide2(const void* fin, void* fout, const double* force, LbmDims d,
-                                  double tau0, double cs, double mu, int storage, hipStream_t s);
+                                  double tau0, double cs, double mu, int storage, hipStream_t s,
+                                  void* fmid = nullptr);
 // One problem of a batched forecast step: its state buffers (storage layout),
 // force, sizes, relaxation parameters and its first tile in the batch.
 struct LbmTask {

@@ -256,7 +256,7 @@ __device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
                                               double* __restrict__ fout,
                                               const double* __restrict__ force, int nx, int ny,
                                               int members, double tau0, double smag, double mu,
-                                              int b) {
+                                              int b, double* __restrict__ fmid) {
     extern __shared__ double mid[];  // [kTwoR * kTwoR][9][kTwoMG]
     using T = double;
     const int groups = members / kTwoMG;
@@ -283,10 +283,16 @@ __device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
     collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
     for (int a = 0; a < 9; ++a) mid[(r * 9 + a) * kTwoMG + threadIdx.x] = PopIO<T>::round(f[a], a);
+    const int ix = rx - 1, iy = ry - 1;
+    const bool own = ix >= 0 && ix < kTwoT && iy >= 0 && iy < kTwoT && x0 + ix < nx && y0 + iy < ny;
+    // the first step's state of the tile's own nodes, when asked for
+    if (fmid && own) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fmid + slot(node, a, m, members), a, f[a]);
+    }
     __syncthreads();
     // second step for the tile's own nodes
-    const int ix = rx - 1, iy = ry - 1;
-    if (ix < 0 || ix >= kTwoT || iy < 0 || iy >= kTwoT || x0 + ix >= nx || y0 + iy >= ny) return;
+    if (!own) return;
 #pragma unroll
     for (int a = 0; a < 9; ++a)
         f[a] = mid[(((ry - cy_of(a)) * kTwoR + rx - cx_of(a)) * 9 + a) * kTwoMG + threadIdx.x];
@@ -297,8 +303,8 @@ __device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
 
 __global__ __launch_bounds__(kTwoMG * kTwoR * kTwoR) void stream_collide2_kernel(
     const double* __restrict__ fin, double* __restrict__ fout, const double* __restrict__ force,
-    int nx, int ny, int members, double tau0, double smag, double mu) {
-    two_step_body(fin, fout, force, nx, ny, members, tau0, smag, mu, blockIdx.x);
+    int nx, int ny, int members, double tau0, double smag, double mu, double* __restrict__ fmid) {
+    two_step_body(fin, fout, force, nx, ny, members, tau0, smag, mu, blockIdx.x, fmid);
 }
 
 // The two-step kernel for FP32 storage: the FP32 relaxation on deviations
@@ -315,7 +321,7 @@ __device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
                                                   float* __restrict__ fout,
                                                   const double* __restrict__ force, int nx, int ny,
                                                   int members, float tau0, float smag, float mu,
-                                                  int b, int gsize) {
+                                                  int b, int gsize, float* __restrict__ fmid) {
     extern __shared__ float mids[];  // [kTwoR * kTwoR][9][MG]
     typedef float f2 __attribute__((ext_vector_type(2)));
     const int groups = members / gsize;
@@ -351,10 +357,21 @@ __device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
         v.y = g1[a];
         *reinterpret_cast<f2*>(mids + (r * 9 + a) * MG + mp) = v;
     }
-    __syncthreads();
     const int ix = rx - 1, iy = ry - 1;
-    if (!on) return;
-    if (ix < 0 || ix >= kTwoT || iy < 0 || iy >= kTwoT || x0 + ix >= nx || y0 + iy >= ny) return;
+    const bool own = on && ix >= 0 && ix < kTwoT && iy >= 0 && iy < kTwoT && x0 + ix < nx &&
+                     y0 + iy < ny;
+    // the first step's state of the tile's own nodes, when asked for
+    if (fmid && own) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            f2 v;
+            v.x = g0[a];
+            v.y = g1[a];
+            __builtin_nontemporal_store(v, reinterpret_cast<f2*>(fmid + slot(node, a, m, members)));
+        }
+    }
+    __syncthreads();
+    if (!own) return;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const f2 v = *reinterpret_cast<const f2*>(
@@ -376,8 +393,8 @@ __device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
 template <int MG>
 __global__ __launch_bounds__(MG / 2 * kTwoR * kTwoR) void stream_collide2_dev_kernel(
     const float* __restrict__ fin, float* __restrict__ fout, const double* __restrict__ force,
-    int nx, int ny, int members, float tau0, float smag, float mu) {
-    two_step_dev_body<MG>(fin, fout, force, nx, ny, members, tau0, smag, mu, blockIdx.x, MG);
+    int nx, int ny, int members, float tau0, float smag, float mu, float* __restrict__ fmid) {
+    two_step_dev_body<MG>(fin, fout, force, nx, ny, members, tau0, smag, mu, blockIdx.x, MG, fmid);
 }
 
 // Two steps of many problems in one launch: block b belongs to the task k
@@ -395,12 +412,13 @@ stream_collide2_batch_kernel(const LbmTask* __restrict__ tasks, int ntasks) {
     const LbmTask& tk = tasks[k];
     if constexpr (sizeof(T) == 8)
         two_step_body(static_cast<const double*>(tk.fin), static_cast<double*>(tk.fout), tk.force,
-                      tk.nx, tk.ny, tk.members, tk.tau0, tk.smag, tk.mu, b - tk.block0);
+                      tk.nx, tk.ny, tk.members, tk.tau0, tk.smag, tk.mu, b - tk.block0, nullptr);
     else
         two_step_dev_body<kTwoMG32>(static_cast<const float*>(tk.fin),
                                     static_cast<float*>(tk.fout), tk.force, tk.nx, tk.ny,
                                     tk.members, (float)tk.tau0, (float)tk.smag, (float)tk.mu,
-                                    b - tk.block0, tk.members % kTwoMG32 == 0 ? kTwoMG32 : kTwoMG);
+                                    b - tk.block0, tk.members % kTwoMG32 == 0 ? kTwoMG32 : kTwoMG,
+                                    nullptr);
 }
 
 // storage slot (node (x, y), a, m) <- canonical [m][a][y + c_ay][x + c_ax]
@@ -521,7 +539,8 @@ bool two_step_supported(LbmDims d, int storage) {
 }
 
 hipError_t launch_stream_collide2(const void* fin, void* fout, const double* force, LbmDims d,
-                                  double tau0, double cs, double mu, int storage, hipStream_t s) {
+                                  double tau0, double cs, double mu, int storage, hipStream_t s,
+                                  void* fmid) {
     if (!two_step_supported(d, storage)) return hipErrorInvalidValue;
     const int tiles = ((d.nx + kTwoT - 1) / kTwoT) * ((d.ny + kTwoT - 1) / kTwoT);
     const double smag = 18.0 * sqrt(2.0) * cs * cs;
@@ -538,7 +557,7 @@ hipError_t launch_stream_collide2(const void* fin, void* fout, const double* for
             stream_collide2_dev_kernel<32><<<tiles * (d.members / 32), dim3(16, kTwoR * kTwoR),
                                              bytes, s>>>((const float*)fin, (float*)fout, force,
                                                          d.nx, d.ny, d.members, (float)tau0,
-                                                         (float)smag, (float)mu);
+                                                         (float)smag, (float)mu, (float*)fmid);
         } else {
             const size_t bytes = (size_t)kTwoR * kTwoR * 9 * 16 * sizeof(float);
             if (!attr16)
@@ -549,7 +568,7 @@ hipError_t launch_stream_collide2(const void* fin, void* fout, const double* for
             stream_collide2_dev_kernel<16><<<tiles * (d.members / 16), dim3(8, kTwoR * kTwoR),
                                              bytes, s>>>((const float*)fin, (float*)fout, force,
                                                          d.nx, d.ny, d.members, (float)tau0,
-                                                         (float)smag, (float)mu);
+                                                         (float)smag, (float)mu, (float*)fmid);
         }
         return hipGetLastError();
     }
@@ -562,7 +581,8 @@ hipError_t launch_stream_collide2(const void* fin, void* fout, const double* for
     if (e != hipSuccess) return e;
     attr = true;
     stream_collide2_kernel<<<grid, block, bytes, s>>>(
-        (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu);
+        (const double*)fin, (double*)fout, force, d.nx, d.ny, d.members, tau0, smag, mu,
+        (double*)fmid);
     return hipGetLastError();
 }
 
