@@ -60,6 +60,14 @@ def traffic_record(kernel: str):
     return None
 
 
+def two_step_bytes(n: int, members: int, elem: int) -> int:
+    """Algorithmic bytes of one two-step launch over an n x n grid: per member,
+    every 6 x 6 tile's 8 x 8 node region read once (9 populations) and the
+    interior written once; the intermediate step stays on chip."""
+    tiles = (-(-n // 6)) ** 2
+    return members * (tiles * 64 + n * n) * 9 * elem
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -281,6 +289,22 @@ def median_run(runs):
     return sorted(runs, key=lambda r: r[0])[len(runs) // 2]
 
 
+def f32_forecast_roofline(cfg, t_step: float) -> dict:
+    """The FP32 two-step forecast kernel (stream_collide2_dev) against the HBM
+    roofline at its own bytes; `t_step` is the library's per-step time (two
+    steps per launch when 16 divides the member count)."""
+    two = cfg.members % 16 == 0
+    t = t_step * (2 if two else 1)
+    b = two_step_bytes(cfg.n, cfg.members, 4) if two else 72 * cfg.n * cfg.n * cfg.members
+    kname = "stream_collide2_dev_kernel" if two else "stream_collide_kernel"
+    rec = traffic_record(kname) if two and cfg.name == "paper" else None
+    gbs = b / t / 1e9
+    return {"kernel": kname.replace("_kernel", ""), "bound": "hbm", "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": rec["bytes_per_launch"] if rec else None, "algorithmic_bytes": int(b),
+            "steps_per_launch": 2 if two else 1, "avg_launch_us": round(t * 1e6, 2)}
+
+
 def precision_config_form(cycles: int):
     """The precision form at its own configuration (512^2, 64 members, 16x16
     (u, v) observations, s = 20) beside the plain FP64 form on the same
@@ -313,6 +337,9 @@ def precision_config_form(cycles: int):
         out[f"{name}_cycles_per_s"] = round(steps / el, 3)
         out[f"{name}_stream_collide_us_per_step"] = round(1e3 * ms[0] / max(n[0], 1), 2)
         out[f"{name}_analysis_ms"] = round(ms[3] / max(n[3], 1), 4)
+        if storage == binding.STORAGE_F32_DEV and not mfma:
+            out[f"{name}_roofline_forecast"] = f32_forecast_roofline(cfg, 1e-3 * ms[0]
+                                                                     / max(n[0], 1))
         if g is not None:
             spec, dall = spectra_pass(ctx, cfg, yo_all, tuv_all, report)
             out[f"{name}_vs_fp64_oracle"] = versus_oracle(g, dall, spec, cfg.n, cycles)
@@ -463,9 +490,16 @@ def batching_form(cycles: int, warmup: int):
     same = all(torch.equal(a, b) for a, b in zip(states, seq_states))
     maxdiff = max(float((a.double() - b.double()).abs().max()) for a, b in zip(states, seq_states))
     batch.close()
-    fc_bytes = 72.0 * node_members
-    rec = traffic_record("stream_collide_batch_kernel")
-    gbs = fc_bytes / (fms * 1e-3) / 1e9
+    # the tuner's forecast time is per step; with two steps per launch the
+    # launch is priced at the two-step kernel's own bytes (region read once,
+    # interior written once), else at one step's 72 B per node-member (FP32)
+    two = int(cfg_best.get("steps_per_launch", 1)) == 2
+    fc_bytes = (sum(two_step_bytes(c.n, c.members, 4) for c in cfgs) if two
+                else 72.0 * node_members)
+    t_fc = fms * 1e-3 * (2 if two else 1)
+    kname = "stream_collide2_batch_kernel" if two else "stream_collide_batch_kernel"
+    rec = traffic_record(kname)
+    gbs = fc_bytes / t_fc / 1e9
     return {
         "workload": ("12 problems: grids {128,192,256,384}^2 x members {16,32,64}, "
                      "observation grids 4x4..32x32, 0-44 local observations, FP32 f - w, s=20"),
@@ -479,12 +513,13 @@ def batching_form(cycles: int, warmup: int):
         "tuned_analysis_ms": round(ams, 4),
         "states_equal_to_sequential": same,
         "max_abs_state_diff_vs_sequential": maxdiff,
-        "roofline_forecast": {"kernel": "stream_collide_batch", "bound": "hbm",
+        "roofline_forecast": {"kernel": kname.replace("_kernel", ""), "bound": "hbm",
                               "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(gbs / HBM_PEAK_GBS, 4),
                               "traffic": rec["bytes_per_launch"] if rec else None,
                               "algorithmic_bytes": int(fc_bytes),
-                              "avg_launch_us": round(fms * 1e3, 2)},
+                              "steps_per_launch": 2 if two else 1,
+                              "avg_launch_us": round(t_fc * 1e6, 2)},
     }
 
 
@@ -604,6 +639,7 @@ def main() -> int:
             "cycles_per_s": round(args.steps / el32, 3),
             "speedup_vs_plain": round(elapsed / el32, 4),
             "stream_collide_us_per_step": round(1e3 * ms32[0] / max(n32[0], 1), 2),
+            "roofline_forecast": f32_forecast_roofline(cfg, 1e-3 * ms32[0] / max(n32[0], 1)),
             "rmse_a_mean": float(d32[:, binding.DIAG_LEN].mean()),
             "max_abs_rmse_a_diff_vs_plain": float(np.max(np.abs(
                 d32[:, binding.DIAG_LEN] - d[:, binding.DIAG_LEN]))),
@@ -645,8 +681,7 @@ def main() -> int:
         # the two-step launch's own algorithmic bytes: per 16-member block, the
         # 8 x 8 node region read once (9 FP64 pulls per node) and the 6 x 6
         # interior written once; the intermediate step stays in LDS
-        tiles = -(-cfg.n // 6) * -(-cfg.n // 6)
-        kernel_bytes = cfg.members * (tiles * 64 * 72 + plane * 72)
+        kernel_bytes = two_step_bytes(cfg.n, cfg.members, 8)
     else:
         kernel_bytes = single_step_bytes
     kernel_gbs = kernel_bytes / t_launch / 1e9
