@@ -406,12 +406,19 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
 // with whole rows beats one node with half rows in a wavefront (measured 103
 // against 134 ns per node at 64 members).  Up to N = 18 the eigensolver fits
 // in 168 VGPRs (three wavefronts per SIMD) without spilling; larger N keep the
-// compiler's choice.
+// compiler's choice (three up to N = 24).  Four wavefronts per SIMD (128
+// VGPRs: no spill inside the sweeps at N = 18, a few at N = 20 and 22) were
+// measured no faster at N = 18 and 2-4 % slower overall when extended to
+// N = 20 and 22: the sweeps are bound by the LDS traffic of the row exchange
+// and the rotation broadcast, not by latency.
 template <int N>
 constexpr bool kSplitRows = N > 32;
 
 template <int N>
 constexpr int eig_threads() { return kSplitRows<N> ? 2 * kWave : kWave; }
+
+template <int N>
+constexpr int eig_waves() { return N <= 18 ? 3 : 1; }
 
 template <int N>
 constexpr int eig_lds_doubles() {
@@ -420,7 +427,7 @@ constexpr int eig_lds_doubles() {
 }
 
 template <int N>
-__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
+__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(eig_waves<N>())))
 void analysis_eig_kernel(AnalysisParams p, const int* nodes, int count, double* gout) {
     if constexpr (kSplitRows<N>)
         eig_body_split<N>(p, nodes, xcd_remap(blockIdx.x, gridDim.x), count, gout);
@@ -431,7 +438,7 @@ void analysis_eig_kernel(AnalysisParams p, const int* nodes, int count, double* 
 // Batched form: wavefront w takes waves[w] = (problem, first item, end of the
 // problem's items); the items of all problems share one node list and one G buffer.
 template <int N>
-__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 18 ? 3 : 1)))
+__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(eig_waves<N>())))
 void analysis_eig_batch_kernel(const AnalysisParams* P, const int4* waves, int nwaves,
                                const int* nodes, double* gout) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
