@@ -113,25 +113,43 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(
     double lk = 0.0;
     if (node < plane) {
         const int y = node / nx, x = node - y * nx;
+        const int xm = wrap(x - 1, nx), xp = wrap(x + 1, nx);
+        const int ym = wrap(y - 1, ny), yp = wrap(y + 1, ny);
+        // forward state: canonical f_a(y) is held by the slot of node y - c_a
+        const PullSlots<const T> fsrc(fstate, x, xm, xp, y, ym, yp, nx, members, m);
+        // adjoint of f^{n+1}_a at the node this population streams to, y + c_a
+        // (the same addressing with the neighbours swapped)
+        const PullSlots<const double> lsrc(lam_in, x, xp, xm, y, yp, ym, nx, members, m);
         double f[9], L[9], Lf[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            // forward state: canonical f_a(y) is held by the slot of node y - c_a
-            f[a] = PopIO<T>::load(fstate + slot(src_node(x, y, a, nx, ny), a, m, members), a);
-            // adjoint of f^{n+1}_a at the node this population streams to, y + c_a
-            const size_t dst = (size_t)wrap(y + cy_of(a), ny) * nx + wrap(x + cx_of(a), nx);
-            L[a] = lam_in[slot(dst, a, m, members)];
+            f[a] = PopIO<T>::load(fsrc.at(a), a);
+            L[a] = *lsrc.at(a);
         }
         const double fx = force ? force[node] : 0.0, fy = force ? force[plane + node] : 0.0;
         lk = collide_vjp(f, L, tau0, K, fx, fy, mu, Lf);
+        double* const out = lam_out + (size_t)node * 9 * members + m;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) lam_out[slot(node, a, m, members)] = Lf[a];
+        for (int a = 0; a < 9; ++a) out[(uint32_t)a * members] = Lf[a];
     }
     // per-block sum of dJ/dK, accumulated in this block's own slot (launches
     // on one stream are ordered, so the accumulation is deterministic)
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const int nthreads = blockDim.x * blockDim.y;
     __shared__ double red[kBlock];
+    if (nthreads % kWave == 0) {
+        // whole wavefronts (M a power of two): a DPP sum per wavefront, then
+        // the wavefront sums in order, one barrier
+        const double ws = wave_sum(lk);
+        if (tid % kWave == 0) red[tid / kWave] = ws;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < nthreads / kWave; ++w) t += red[w];
+            k_partial[blockIdx.x] += t;
+        }
+        return;
+    }
     red[tid] = lk;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {

@@ -162,6 +162,8 @@ lbmletkf_status check_lbm(const lbmletkf_lbm_params* p) {
         return fail(LBMLETKF_ESHAPE, "grid too large (nx*ny must be < 2^28)");
     if (p->members < 1 || p->members > 64)
         return fail(LBMLETKF_ESHAPE, "members must be in 1..64");
+    if ((int64_t)p->nx * 9 * p->members >= (int64_t)1 << 31)
+        return fail(LBMLETKF_ESHAPE, "nx * 9 * members must be < 2^31 (the slots of one lattice row)");
     if (!(p->tau0 > 0.5) || !std::isfinite(p->tau0))
         return fail(LBMLETKF_EINVAL, "tau0 must be finite and > 1/2");
     if (!(p->cs >= 0.0) || !std::isfinite(p->cs)) return fail(LBMLETKF_EINVAL, "cs must be >= 0");

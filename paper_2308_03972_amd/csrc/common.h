@@ -37,6 +37,37 @@ __host__ __device__ __forceinline__ int wrap1(int i, int n) {
 __host__ __device__ __forceinline__ size_t src_node(int x, int y, int a, int nx, int ny) {
     return (size_t)wrap1(y - cy_of(a), ny) * nx + wrap1(x - cx_of(a), nx);
 }
+// The storage slots a thread of node (x, y), member m pulls from: the slot of
+// population a at node (x - c_ax, y - c_ay).  Three row pointers (64-bit, one
+// multiply each) and three column offsets within a row (32-bit: a lattice row
+// holds nx * 9 * members < 2^31 slots, checked when a context is created), so
+// that each of the nine sources costs a 32-bit add and a pointer add instead
+// of a 64-bit multiply-add chain (60-130 fewer instructions per thread in the
+// forecast and adjoint kernels; their time did not change: they wait on
+// memory, not on issue).  xm, xp, ym, yp: the wrapped neighbours x - 1, x + 1, ...
+template <typename P>
+struct PullSlots {
+    P* rows[3];       // row y - c_ay, indexed c_ay + 1
+    uint32_t cols[3]; // column offset (x - c_ax) * 9 M + m, indexed c_ax + 1
+    uint32_t members;
+    __device__ __forceinline__ PullSlots(P* base, int x, int xm, int xp, int y, int ym, int yp,
+                                         int nx, int members_, int m)
+        : members((uint32_t)members_) {
+        const size_t row = (size_t)nx * 9 * members_;
+        rows[0] = base + (size_t)yp * row;
+        rows[1] = base + (size_t)y * row;
+        rows[2] = base + (size_t)ym * row;
+        const uint32_t node = 9u * members;
+        cols[0] = (uint32_t)xp * node + (uint32_t)m;
+        cols[1] = (uint32_t)x * node + (uint32_t)m;
+        cols[2] = (uint32_t)xm * node + (uint32_t)m;
+    }
+    // a: a compile-time constant after unrolling
+    __device__ __forceinline__ P* at(int a) const {
+        return rows[cy_of(a) + 1] + (cols[cx_of(a) + 1] + (uint32_t)a * members);
+    }
+};
+
 // Node-member launches: blocks of (members, nodes_per_block) threads.
 inline int nodes_per_block(int members) { return members >= 256 ? 1 : 256 / members; }
 

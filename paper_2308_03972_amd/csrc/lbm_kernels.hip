@@ -95,16 +95,27 @@ __device__ __forceinline__ void collide_node_dev(float (&g)[9], float tau0, floa
     const float rho = 1.0f + drho;
     const float jx = (g[1] - g[2]) + (g[5] - g[6]) + (g[7] - g[8]);
     const float jy = (g[3] - g[4]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const float inv_rho = 1.0f / rho;
+    // 1 / rho: the hardware reciprocal (1 ulp) refined by one Newton step, three
+    // instructions instead of the correctly rounded division's ten (the bare
+    // reciprocal biases u enough to move a 200-step misfit by 4e-6 relative);
+    // the square roots below are the hardware ones (|Pi| and R only need their
+    // own relative accuracy)
+    float inv_rho = __builtin_amdgcn_rcpf(rho);
+    inv_rho = fmaf(inv_rho, fmaf(-rho, inv_rho, 1.0f), inv_rho);
     const float u = jx * inv_rho, v = jy * inv_rho;
     const float uu = u * u, vv = v * v, uv = u * v;
     const float d3 = drho * (1.0f / 3.0f);
     const float pxx = fmaf(-rho, uu, (g[1] + g[2] + g[5] + g[6] + g[7] + g[8]) - d3);
     const float pyy = fmaf(-rho, vv, (g[3] + g[4] + g[5] + g[6] + g[7] + g[8]) - d3);
     const float pxy = fmaf(-rho, uv, g[5] + g[6] - g[7] - g[8]);
-    const float pn = sqrtf(fmaf(pxx, pxx, fmaf(pyy, pyy, (2.0f * pxy) * pxy)));
-    const float tau = 0.5f * (tau0 + sqrtf(fmaf(tau0, tau0, (smag * pn) * inv_rho)));
-    const float omega = 1.0f / tau;
+    const float pn = __builtin_amdgcn_sqrtf(fmaf(pxx, pxx, fmaf(pyy, pyy, (2.0f * pxy) * pxy)));
+    // omega = 1 / tau = 2 / (tau0 + R), R = sqrt(tau0^2 + x), x = 18 sqrt(2) C_s^2 |Pi| / rho,
+    // taken as the molecular 1 / tau0 minus the eddy part x / (tau0 (tau0 + R)^2),
+    // which FP32 then carries to its own relative accuracy (as 1 / tau the eddy
+    // part, often 1e-4 of omega, would keep only a few bits)
+    const float x = (smag * pn) * inv_rho;
+    const float tr = tau0 + __builtin_amdgcn_sqrtf(fmaf(tau0, tau0, x));
+    const float omega = 1.0f / tau0 - x * __builtin_amdgcn_rcpf(tau0 * tr * tr);
     const float gx = fmaf(-mu, u, fx_ext), gy = fmaf(-mu, v, fy_ext);
     const float usq = -1.5f * (uu + vv);
 #pragma unroll
@@ -133,10 +144,9 @@ __device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restr
     const int y = node / nx, x = node - y * nx;
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-    const size_t rc = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
-    // node holding the canonical f_a(x, y): (x - c_ax, y - c_ay)
-    const size_t src[9] = {rc + x,  rc + xm, rc + xp, rm + x, rp + x,
-                           rm + xm, rp + xp, rp + xm, rm + xp};
+    // slots holding the canonical f_a(x, y): node (x - c_ax, y - c_ay)
+    const PullSlots<const T> src(fin, x, xm, xp, y, ym, yp, nx, members, m);
+    T* const dst = fout + (size_t)node * 9 * members + m;
     double fx = 0.0, fy = 0.0;
     if (force) {
         fx = force[node];
@@ -147,22 +157,22 @@ __device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restr
     if constexpr (sizeof(T) == 8) {
         double f[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(fin + slot(src[a], a, m, members), a);
+        for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(src.at(a), a);
         collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
+        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(dst + (uint32_t)a * members, a, f[a]);
     } else {
         // FP32 deviations: the FP32 relaxation on g = f - w, no conversion
         float g[V][9];
         if constexpr (V == 1) {
 #pragma unroll
             for (int a = 0; a < 9; ++a)
-                g[0][a] = __builtin_nontemporal_load(fin + slot(src[a], a, m, members));
+                g[0][a] = __builtin_nontemporal_load(src.at(a));
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 const float2v p = __builtin_nontemporal_load(
-                    reinterpret_cast<const float2v*>(fin + slot(src[a], a, m, members)));
+                    reinterpret_cast<const float2v*>(src.at(a)));
                 g[0][a] = p.x;
                 g[1][a] = p.y;
             }
@@ -173,14 +183,14 @@ __device__ __forceinline__ void lbm_update(const T* __restrict__ fin, T* __restr
         if constexpr (V == 1) {
 #pragma unroll
             for (int a = 0; a < 9; ++a)
-                __builtin_nontemporal_store(g[0][a], fout + slot(node, a, m, members));
+                __builtin_nontemporal_store(g[0][a], dst + (uint32_t)a * members);
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 float2v p;
                 p.x = g[0][a];
                 p.y = g[1][a];
-                __builtin_nontemporal_store(p, reinterpret_cast<float2v*>(fout + slot(node, a, m, members)));
+                __builtin_nontemporal_store(p, reinterpret_cast<float2v*>(dst + (uint32_t)a * members));
             }
         }
     }
@@ -275,11 +285,13 @@ __device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
         fx = force[node];
         fy = force[plane + node];
     }
+    const PullSlots<const T> src(fin, gx, wrap_dec(gx, nx), wrap_inc(gx, nx), gy, wrap_dec(gy, ny),
+                                 wrap_inc(gy, ny), nx, members, m);
+    const size_t own_slot = (size_t)node * 9 * members + m;
     // first step: the single step's pull and collision
     double f[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a)
-        f[a] = PopIO<T>::load_nt(fin + slot(src_node(gx, gy, a, nx, ny), a, m, members), a);
+    for (int a = 0; a < 9; ++a) f[a] = PopIO<T>::load_nt(src.at(a), a);
     collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
     for (int a = 0; a < 9; ++a) mid[(r * 9 + a) * kTwoMG + threadIdx.x] = PopIO<T>::round(f[a], a);
@@ -288,7 +300,8 @@ __device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
     // the first step's state of the tile's own nodes, when asked for
     if (fmid && own) {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fmid + slot(node, a, m, members), a, f[a]);
+        for (int a = 0; a < 9; ++a)
+            PopIO<T>::store_nt(fmid + own_slot + (uint32_t)a * members, a, f[a]);
     }
     __syncthreads();
     // second step for the tile's own nodes
@@ -298,7 +311,7 @@ __device__ __forceinline__ void two_step_body(const double* __restrict__ fin,
         f[a] = mid[(((ry - cy_of(a)) * kTwoR + rx - cx_of(a)) * 9 + a) * kTwoMG + threadIdx.x];
     collide_node(f, tau0, smag, fx, fy, mu);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + slot(node, a, m, members), a, f[a]);
+    for (int a = 0; a < 9; ++a) PopIO<T>::store_nt(fout + own_slot + (uint32_t)a * members, a, f[a]);
 }
 
 __global__ __launch_bounds__(kTwoMG * kTwoR * kTwoR) void stream_collide2_kernel(
@@ -340,11 +353,13 @@ __device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
         fx = (float)force[node];
         fy = (float)force[plane + node];
     }
+    const PullSlots<const float> src(fin, gx, wrap_dec(gx, nx), wrap_inc(gx, nx), gy,
+                                     wrap_dec(gy, ny), wrap_inc(gy, ny), nx, members, m);
+    const size_t own_slot = (size_t)node * 9 * members + m;
     float g0[9], g1[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const f2 v = __builtin_nontemporal_load(
-            reinterpret_cast<const f2*>(fin + slot(src_node(gx, gy, a, nx, ny), a, m, members)));
+        const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(src.at(a)));
         g0[a] = v.x;
         g1[a] = v.y;
     }
@@ -367,7 +382,8 @@ __device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
             f2 v;
             v.x = g0[a];
             v.y = g1[a];
-            __builtin_nontemporal_store(v, reinterpret_cast<f2*>(fmid + slot(node, a, m, members)));
+            __builtin_nontemporal_store(
+                v, reinterpret_cast<f2*>(fmid + own_slot + (uint32_t)a * members));
         }
     }
     __syncthreads();
@@ -386,7 +402,7 @@ __device__ __forceinline__ void two_step_dev_body(const float* __restrict__ fin,
         f2 v;
         v.x = g0[a];
         v.y = g1[a];
-        __builtin_nontemporal_store(v, reinterpret_cast<f2*>(fout + slot(node, a, m, members)));
+        __builtin_nontemporal_store(v, reinterpret_cast<f2*>(fout + own_slot + (uint32_t)a * members));
     }
 }
 
