@@ -1277,7 +1277,7 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
                                        (size_t)r.count});
                 for (int i = 0; i < r.count; i += segs) ew.push_back(make_int4(r.k, base + i, base + r.count, 0));
                 for (int i = 0; i < r.count; ++i) aw.push_back(make_int2(r.k, base + i));
-                grp.cost += (double)r.count * ((double)sz * sz * sz + 3000.0);
+                grp.cost += (double)r.count * obs_node_cost(sz);
                 base += r.count;
             }
             grp.n_eig = (int)ew.size();
@@ -1299,7 +1299,7 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
                 const int plane = c->dims.nx * c->dims.ny;
                 for (int i = 0; i < plane; i += ens_segments(sz)) w.push_back(make_int2(k, i));
                 grp.nz_max = std::max(grp.nz_max, c->obs.nvar * c->lmax);
-                grp.cost += (double)plane * 4.0 * sz * sz * sz;
+                grp.cost += (double)plane * ens_node_cost(sz);
             }
             grp.n_waves = (int)w.size();
             grp.waves = reinterpret_cast<int2*>(take(w.size() * sizeof(int2)));
@@ -1324,7 +1324,10 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "batch waves");
-    // longest processing time first over the launch stream and the side streams
+    // longest processing time first over the launch stream and the side streams,
+    // on the measured per-node costs of each route and size (the two routes'
+    // kernels differ too much for a common N^3 model: the packed 16-member
+    // ensemble route costs 1/44 of a 48-observation node)
     std::vector<int> order(b->groups.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(),
