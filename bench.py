@@ -91,11 +91,16 @@ _CPU_JOB = {}
 
 
 def _cpu_analysis_chunk(nodes):
-    """Worker: the oracle analysis of `nodes`, written into the shared output."""
+    """Worker: the oracle analysis of `nodes`, written into the shared output.
+    One BLAS thread per worker: the workers already fill the cores, and
+    NumPy's BLAS would otherwise start OMP_NUM_THREADS threads in each."""
     import oracle
+    from threadpoolctl import threadpool_limits
     j = _CPU_JOB
-    j["out"][:, :, nodes] = oracle.letkf_analysis(j["f"], j["yf"], j["yo"], j["pts"], j["sigmas"],
-                                                  j["d_cut"], j["beta"], nodes=nodes)
+    with threadpool_limits(limits=1):
+        j["out"][:, :, nodes] = oracle.letkf_analysis(j["f"], j["yf"], j["yo"], j["pts"],
+                                                      j["sigmas"], j["d_cut"], j["beta"],
+                                                      nodes=nodes)
     return len(nodes)
 
 
@@ -145,9 +150,11 @@ def cpu_baseline(cfg, force, pts, sample_cycles: int, procs: int):
     except OSError:
         pass
     yf = oracle.observe(fe, pts, cfg.nvar)
+    from threadpoolctl import threadpool_limits
     t0 = time.perf_counter()
-    oracle.letkf_analysis(fe, yf, yf.mean(axis=0), pts, cfg.sigmas, cfg.d_cut, cfg.beta,
-                          nodes=nodes[:2048])
+    with threadpool_limits(limits=1):
+        oracle.letkf_analysis(fe, yf, yf.mean(axis=0), pts, cfg.sigmas, cfg.d_cut, cfg.beta,
+                              nodes=nodes[:2048])
     t_node1 = (time.perf_counter() - t0) / 2048
     return {
         "value": 1.0 / t_cycle, "unit": "cycles/s", "cores": max(threads, procs), "kind": "oracle",
