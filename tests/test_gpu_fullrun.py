@@ -9,7 +9,8 @@ ensemble at sampled nodes.  The GPU side runs the same configuration through
 the C ABI: the truth on an M = 1 context, observations y^o = H(truth) +
 sigma * eps from the same seeded noise, run_cycle per cycle.
 
-Bars (SURVEY C12 reading, the benchmark spec tolerances):
+Bars (FP64: rounding-level agreement of two FP64 implementations; FP32: the
+precision form's accuracy target, 1e-3 of the observation error):
   FP64 storage   per-cycle RMSE_f, RMSE_a, spread relative difference < 1e-6
                  over every cycle; final state at the sampled nodes <= 1e-9
                  of the state's scale; spectrum error max over 1 <= k <= n/3 of
