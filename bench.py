@@ -750,6 +750,10 @@ def main() -> int:
         "repeats_cycles_per_s": [round(args.steps / r[0], 3) for r in runs],
         "glups_member": round(glups, 3),
         "glups_member_stream_collide": round(plane * cfg.members / t_lbm / 1e9, 3),
+        # the analysis alone: whole-grid analyses per second and local (per-node)
+        # LETKF problems solved per second, from its event-timed share of the cycle
+        "analyses_per_s": round(1.0 / t_an, 1),
+        "node_analyses_per_s": round(plane / t_an, 1),
         "rmse_a_mean": float(rmse_a.mean()),
         "rmse_f_mean": float(rmse_f.mean()),
         "spread_a_mean": float(d[:, binding.DIAG_LEN + 1].mean()),
