@@ -299,9 +299,10 @@ lbmletkf_status lbmletkf_local_histogram(lbmletkf_ctx* ctx, int32_t* hist, int32
  * The adjoint workspace (device, caller-owned, 256-byte aligned, at least
  * lbmletkf_adjoint_workspace_bytes; separate from the context's workspace)
  * holds the state at every observation time (the checkpoints; a checkpoint
- * every steps_per_obs steps), the steps_per_obs - 1 states between two
- * checkpoints that the reverse sweep recomputes, two FP64 adjoint states and
- * the partial sums.  lbmletkf_misfit_forward writes the checkpoints;
+ * every steps_per_obs steps), two sets of the steps_per_obs - 1 states between
+ * two checkpoints that the reverse sweep recomputes (one interval is
+ * recomputed on a library-owned stream while the caller's stream runs the
+ * adjoint steps of the next), two FP64 adjoint states and the partial sums.  lbmletkf_misfit_forward writes the checkpoints;
  * lbmletkf_misfit_backward reads them, so call it after a forward call with
  * the same d_f0, cs, steps_per_obs, n_times and workspace (checked; the
  * contents of d_f0, d_yo and the workspace must not change in between, which

@@ -81,6 +81,11 @@ struct Ctx {
         int steps = 0, times = 0;
         const void* work = nullptr;
     } fwd;
+    // the reverse sweep recomputes the next interval's states on this stream
+    // while the caller's stream runs the current interval's adjoint steps
+    // (created at the first backward call)
+    hipStream_t rstream = nullptr;
+    hipEvent_t rstart = nullptr, rready[2] = {nullptr, nullptr}, rfree[2] = {nullptr, nullptr};
     // per-stage timing
     int profiling = 0;  // 0 off, 1 every launch, 2 per call: forecast steps and analysis
     struct Rec {
@@ -321,7 +326,7 @@ Layout make_layout(const lbmletkf_lbm_params* p, const lbmletkf_obs_params* o, i
 
 // Adjoint workspace of the misfit sweeps.
 struct AdjLayout {
-    size_t ckpt, seg, lam0, lam1, jbuf, kpart, total;
+    size_t ckpt, seg[2], lam0, lam1, jbuf, kpart, total;
 };
 
 AdjLayout make_adj_layout(const lbmletkf_lbm_params* p, int n_points, int steps, int times) {
@@ -336,7 +341,10 @@ AdjLayout make_adj_layout(const lbmletkf_lbm_params* p, int n_points, int steps,
         return at;
     };
     L.ckpt = take(align_up(sb) * times);
-    L.seg = take(align_up(sb) * (steps - 1));
+    // two sets of the states between checkpoints: the reverse sweep recomputes
+    // one interval into one set while the adjoint steps read the other
+    L.seg[0] = take(align_up(sb) * (steps - 1));
+    L.seg[1] = take(align_up(sb) * (steps - 1));
     L.lam0 = take(lb);
     L.lam1 = take(lb);
     L.jbuf = take((size_t)p->members * n_points * sizeof(double));
@@ -359,6 +367,12 @@ void release_streams(Ctx* c) {
     }
     if (c->fork) (void)hipEventDestroy(c->fork);
     c->fork = nullptr;
+    if (c->rstream) (void)hipStreamDestroy(c->rstream);
+    c->rstream = nullptr;
+    for (hipEvent_t* e : {&c->rstart, &c->rready[0], &c->rready[1], &c->rfree[0], &c->rfree[1]}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
 }
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -868,7 +882,13 @@ struct Sweep {
     size_t sb;
     const void* ckpt(int t) const { return t == 0 ? f0 : w + L.ckpt + (size_t)(t - 1) * sb; }
     void* ckpt_mut(int t) const { return w + L.ckpt + (size_t)(t - 1) * sb; }
-    void* seg(int j) const { return w + L.seg + (size_t)(j - 1) * sb; }
+    int set = 0;  // which of the two sets of intermediate states
+    void* seg(int j) const { return w + L.seg[set] + (size_t)(j - 1) * sb; }
+    Sweep with_set(int k) const {
+        Sweep o = *this;
+        o.set = k;
+        return o;
+    }
 };
 
 // Steps 1 .. last of the segment that starts at checkpoint t - 1, every state
@@ -990,7 +1010,40 @@ lbmletkf_status lbmletkf_misfit_backward(lbmletkf_ctx* ctx, const void* d_f0, do
     hipError_t e = launch_fill(cur, nlam, 0.0, s);
     if (e == hipSuccess) e = launch_fill(kpart, (size_t)nparts, 0.0, s);
     if (e != hipSuccess) return hip_fail(e, "fill");
+    // The states between checkpoints t - 1 and t are recomputed on the
+    // recompute stream into set t % 2, one interval ahead of the adjoint steps
+    // on the caller's stream: interval t - 1 is recomputed while interval t is
+    // reversed, set (t - 1) % 2 being reused once interval t + 1's adjoint
+    // steps are done with it.  Same kernels and inputs, so the same bits.
+    if (!c->rstream) {
+        e = hipStreamCreateWithFlags(&c->rstream, hipStreamNonBlocking);
+        for (hipEvent_t* ev : {&c->rstart, &c->rready[0], &c->rready[1], &c->rfree[0], &c->rfree[1]})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            release_streams(c);
+            return hip_fail(e, "recompute stream");
+        }
+    }
+    hipStream_t rs = c->rstream;
+    e = hipEventRecord(c->rstart, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(rs, c->rstart, 0);
+    if (e != hipSuccess) return hip_fail(e, "recompute fork");
+    auto recompute = [&](int t) -> lbmletkf_status {
+        if (t + 2 <= n_times) {
+            // set t % 2 was last read by interval t + 2's adjoint steps
+            hipError_t ee = hipStreamWaitEvent(rs, c->rfree[t % 2], 0);
+            if (ee != hipSuccess) return hip_fail(ee, "recompute wait");
+        }
+        lbmletkf_status r = segment_steps(c, sw.with_set(t % 2), t, steps_per_obs,
+                                          steps_per_obs - 1, cs, rs);
+        if (r) return r;
+        hipError_t ee = hipEventRecord(c->rready[t % 2], rs);
+        return ee == hipSuccess ? LBMLETKF_OK : hip_fail(ee, "recompute record");
+    };
+    if ((st = recompute(n_times))) return st;
     for (int t = n_times; t >= 1; --t) {
+        if (t > 1 && (st = recompute(t - 1))) return st;
+        const Sweep cw = sw.with_set(t % 2);
         {
             // lam^(t s) += dJ_t/df at the observation nodes
             StageTimer tm(c, kStageMisfit, s);
@@ -999,16 +1052,19 @@ lbmletkf_status lbmletkf_misfit_backward(lbmletkf_ctx* ctx, const void* d_f0, do
                               c->storage(), s);
             if (e != hipSuccess) return hip_fail(e, "misfit");
         }
-        // recompute the states between checkpoints t - 1 and t
-        if ((st = segment_steps(c, sw, t, steps_per_obs, steps_per_obs - 1, cs, s))) return st;
+        // the states between checkpoints t - 1 and t
+        e = hipStreamWaitEvent(s, c->rready[t % 2], 0);
+        if (e != hipSuccess) return hip_fail(e, "recompute join");
         for (int j = steps_per_obs - 1; j >= 0; --j) {
-            const void* state = j == 0 ? sw.ckpt(t - 1) : sw.seg(j);
+            const void* state = j == 0 ? sw.ckpt(t - 1) : cw.seg(j);
             StageTimer tm(c, kStageAdjoint, s);
             e = launch_adjoint_step(state, cur, oth, c->force(), c->dims, c->lbm.tau0, cs,
                                     c->lbm.mu, c->storage(), kpart, s);
             if (e != hipSuccess) return hip_fail(e, "adjoint_step");
             std::swap(cur, oth);
         }
+        e = hipEventRecord(c->rfree[t % 2], s);
+        if (e != hipSuccess) return hip_fail(e, "recompute release");
     }
     e = launch_lam_to_canonical(cur, d_grad_f0, c->dims, s);
     if (e != hipSuccess) return hip_fail(e, "lam_to_canonical");

@@ -129,8 +129,9 @@ def _adjoint_bytes(lib, n, members, storage, n_points, steps, times):
 
 def test_adjoint_workspace_holds_checkpoints_segment_and_adjoints(lib):
     """Differentiation workload (128^2, 16 members, 64 points, 10 times 20 steps
-    apart): 10 checkpoints + 19 recomputed states in the storage type, two FP64
-    adjoint states, per-(member, point) misfit terms and per-block partials."""
+    apart): 10 checkpoints + two sets of 19 recomputed states in the storage type,
+    two FP64 adjoint states, per-(member, point) misfit terms and per-block
+    partials."""
     def align(v):
         return (v + 255) // 256 * 256
     for storage, elem in ((binding.STORAGE_F32_DEV, 4), (binding.STORAGE_F64, 8)):
@@ -138,7 +139,7 @@ def test_adjoint_workspace_holds_checkpoints_segment_and_adjoints(lib):
         assert st == 0
         plane = 128 * 128
         state = align(plane * 9 * 16 * elem)
-        expect = (state * 10 + state * 19 + 2 * align(plane * 9 * 16 * 8)
+        expect = (state * 10 + 2 * state * 19 + 2 * align(plane * 9 * 16 * 8)
                   + align(16 * 64 * 8) + align(16 * (plane // 256) * 8))
         assert nbytes == expect
     st, _ = _adjoint_bytes(lib, 128, 16, 0, 64, 0, 10)
