@@ -43,8 +43,9 @@ __host__ __device__ __forceinline__ size_t src_node(int x, int y, int a, int nx,
 // holds nx * 9 * members < 2^31 slots, checked when a context is created), so
 // that each of the nine sources costs a 32-bit add and a pointer add instead
 // of a 64-bit multiply-add chain (60-130 fewer instructions per thread in the
-// forecast and adjoint kernels; their time did not change: they wait on
-// memory, not on issue).  xm, xp, ym, yp: the wrapped neighbours x - 1, x + 1, ...
+// forecast and adjoint kernels).  The FP32 two-step forecast is issue-bound and
+// gains from it; the FP64 kernels wait on memory and keep their time.
+// xm, xp, ym, yp: the wrapped neighbours x - 1, x + 1, ...
 template <typename P>
 struct PullSlots {
     P* rows[3];       // row y - c_ay, indexed c_ay + 1
