@@ -552,7 +552,7 @@ def main() -> int:
                     help="timed runs of the plain and precision forms (value: the median)")
     ap.add_argument("--precision-cycles", type=int, default=100,
                     help="timed cycles of each form at the precision configuration (512^2)")
-    ap.add_argument("--cpu-cycles", type=int, default=2,
+    ap.add_argument("--cpu-cycles", type=int, default=6,
                     help="whole oracle cycles timed for the CPU baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
