@@ -235,6 +235,224 @@ __device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2*
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same parallel Jacobi with skewed rows: lane i (row i, segment base
+// b = i rounded down to even) keeps column (b + k) mod N of its rows of S and
+// U in register k.  Both lanes of a pair (2m, 2m + 1) then hold the same
+// columns in the same registers, and a_pp, a_pq, a_qq of their 2 x 2 block sit
+// in registers 0 and 1, so a P = 0 round takes the partner's row and the block
+// by DPP quad permutations instead of through LDS; only the rotations (c, s)
+// go through LDS, to every lane of the segment.  P = 1 rounds publish the
+// (skewed) rows as before.  Every entry sees the same operations on the same
+// operands as in the unskewed solver, up to exact sign changes.
+// ---------------------------------------------------------------------------
+// Row stride (doubles) of a skewed published row: the N entries at 2..N+1 with
+// copies of registers N-2, N-1 at 0, 1 and of registers 0, 1 at N+2, N+3, so
+// that a partner's columns are read at a fixed offset; stride/2 odd.
+template <int N>
+struct SkewStride {
+    static constexpr int value = (N % 4 == 2) ? N + 4 : N + 6;
+};
+
+// (c, s) lists of the skewed solver: per segment 2N entries, entry j + N a
+// copy of entry j, so that lane i reads pair (b + k) at b + k without a wrap.
+template <int N, int SEGS>
+__host__ __device__ constexpr int skew_cs_doubles() { return SEGS * 2 * N * 2; }
+
+template <int N, int SEGS, int P>
+__device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N], double* rows,
+                                                  double2* cs2, int lane) {
+    constexpr int RS = SkewStride<N>::value;
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    const bool odd = (i & 1) != 0;
+    const int base = i - (i & 1);
+    double2* csl = cs2 + (size_t)(active ? seg : 0) * 2 * N;
+    const bool first = ((i - P) & 1) == 0;
+    double c, s;
+    if constexpr (P == 0) {
+        // block [[a_pp, a_pq], [a_pq, a_qq]] of pair (2m, 2m + 1): a_pp, a_pq from
+        // the even lane's registers 0, 1 and a_qq from the odd lane's register 1,
+        // the same values in both lanes
+        const double x0 = dpp_partner<0xB1>(S[0]);
+        const double x1 = dpp_partner<0xB1>(S[1]);
+        const double app = odd ? x0 : S[0];
+        const double apq = odd ? x1 : S[1];
+        const double aqq = odd ? S[1] : x1;
+        jacobi_rotation(app, aqq, apq, active, &c, &s);
+        wave_lds_sync();
+        if (active) {
+            csl[i] = make_double2(c, s);
+            csl[i + N] = make_double2(c, s);
+        }
+        // row mix with the partner's row (same columns, same registers)
+        const double sg = first ? s : -s;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double v = dpp_partner<0xB1>(S[k]);
+            S[k] = c * v + sg * S[k];
+        }
+        wave_lds_sync();
+        // column rotation of each pair: registers (2j, 2j + 1) hold columns
+        // (b + 2j, b + 2j + 1) mod N, an even first column
+#pragma unroll
+        for (int j = 0; j < N / 2; ++j) {
+            const double2 q = csl[base + 2 * j];
+            const int r = 2 * j;
+            const double a0 = S[r], a1 = S[r + 1];
+            S[r] = q.y * a0 + q.x * a1;
+            S[r + 1] = q.x * a0 - q.y * a1;
+            const double u0 = U[r], u1 = U[r + 1];
+            U[r] = q.y * u0 + q.x * u1;
+            U[r + 1] = q.x * u0 - q.y * u1;
+        }
+    } else {
+        double* segrows = rows + (size_t)sbase * RS;
+        wave_lds_sync();
+        if (active) {
+            double2* my = reinterpret_cast<double2*>(segrows + (size_t)i * RS);
+            my[0] = make_double2(S[N - 2], S[N - 1]);
+#pragma unroll
+            for (int k = 0; k < N / 2; ++k) my[k + 1] = make_double2(S[2 * k], S[2 * k + 1]);
+            my[N / 2 + 1] = make_double2(S[0], S[1]);
+        }
+        wave_lds_sync();
+        // pair (2m + 1, 2m + 2): a_pp, a_pq are the odd lane's registers 1, 2
+        // (stored at 3, 4), a_qq the even lane's register 0 (stored at 2); a lane
+        // without a partner reads the first pair's block and discards it
+        const int pi = first ? i + 1 : i - 1;
+        const bool paired = active && pi >= 0 && pi < N;
+        const int p = paired ? (first ? i : pi) : 1;
+        // the partner's copy of this lane's column b + k: storage k for an odd
+        // lane (partner base b + 2), k + 4 for an even one (b - 2); a lane
+        // without a partner takes its own row (storage 2 + k) with c = 1, s = 0
+        const int src = paired ? pi : (active ? i : 0);
+        const int off = paired ? (odd ? 0 : 4) : 2;
+        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)src * RS + off);
+        constexpr int KP = N / 2 < 4 ? N / 2 : 4;
+        double2 pre[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) pre[k] = pr[k];
+        jacobi_rotation(segrows[(size_t)p * RS + 3], segrows[(size_t)(p + 1) * RS + 2],
+                        segrows[(size_t)p * RS + 4], paired, &c, &s);
+        // Columns N - 1 and 0, which no rotation pairs in this round, meet in
+        // registers (N - 1 - b, N - b) of every lane, where the pair update
+        // (which swaps as it rotates) runs on them too.  The list entry of
+        // column N - 1, (c, s) = (0, 1), makes that update keep column N - 1
+        // and negate column 0: S D, U D with D = diag(-1, 1, ..., 1).  Lane 0
+        // negates its row, which completes D S D, a similarity; the negations
+        // are exact, so every entry keeps the magnitude the unskewed solver
+        // gives it, and the eigenvectors change sign only.
+        if (active) {
+            const double2 q = i == N - 1 ? make_double2(0.0, 1.0) : make_double2(c, s);
+            csl[i] = q;
+            csl[i + N] = q;
+        }
+        wave_lds_sync();
+        const double sg = first ? s : -s;
+        const double cr = (active && i == 0) ? -1.0 : c;
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) {
+            const double2 v = k < KP ? pre[k < KP ? k : 0] : pr[k];
+            S[2 * k] = cr * v.x + sg * S[2 * k];
+            S[2 * k + 1] = cr * v.y + sg * S[2 * k + 1];
+        }
+        // column pairs (odd first column): registers (k, k + 1) for odd k, and
+        // (N - 1, 0)
+#pragma unroll
+        for (int j = 0; j < N / 2; ++j) {
+            const int r0 = 2 * j + 1, r1 = (2 * j + 2) % N;
+            const double2 q = csl[base + r0];
+            const double a0 = S[r0], a1 = S[r1];
+            S[r0] = q.y * a0 + q.x * a1;
+            S[r1] = q.x * a0 - q.y * a1;
+            const double u0 = U[r0], u1 = U[r1];
+            U[r0] = q.y * u0 + q.x * u1;
+            U[r1] = q.x * u0 - q.y * u1;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) asm volatile("" : "+v"(U[r]), "+v"(S[r]));
+}
+
+// Skewed-row Jacobi: S comes in unskewed (lane i holds row i, register c
+// column c), U is set to the identity, and both go out unskewed; `rows` needs
+// max(SEGS * N * SkewStride<N>, 128) doubles (the rows, and the convergence
+// partial sums between sweeps), `cs2` skew_cs_doubles<N, SEGS>() doubles.
+template <int N, int SEGS>
+__device__ int jacobi_eig_skew(double (&S)[N], double (&U)[N], double* rows, double2* cs2,
+                               int lane, int max_sweeps) {
+    constexpr int RS = SkewStride<N>::value;
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const bool active = seg < SEGS;
+    const int sbase = active ? seg * N : 0;
+    const bool odd = (i & 1) != 0;
+    const int base = i - (i & 1);
+    double* myrow = rows + (size_t)(sbase + (active ? i : 0)) * RS;
+    // skew S through LDS; U = I skewed: column i sits in register i - b
+    wave_lds_sync();
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) myrow[k] = S[k];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int cidx = base + k < N ? base + k : base + k - N;
+        S[k] = active ? myrow[cidx] : 0.0;
+        U[k] = 0.0;
+    }
+    U[0] = (active && !odd) ? 1.0 : 0.0;
+    U[1] = (active && odd) ? 1.0 : 0.0;
+    int result = -1;
+    for (int sweep = 0;; ++sweep) {
+        const double d0 = S[0] * S[0], d1 = S[1] * S[1];
+        double off = odd ? d0 : d1;
+        const double dg = odd ? d1 : d0;
+#pragma unroll
+        for (int r = 2; r < N; ++r) off += S[r] * S[r];
+        wave_lds_sync();
+        rows[2 * lane] = active ? off : 0.0;
+        rows[2 * lane + 1] = active ? dg : 0.0;
+        wave_lds_sync();
+        double so = 0.0, sd = 0.0;
+        for (int k = 0; k < N; ++k) {
+            so += rows[2 * (sbase + k)];
+            sd += rows[2 * (sbase + k) + 1];
+        }
+        const bool done = !active || so <= 1e-26 * sd;
+        if (__all(done)) { result = sweep; break; }
+        if (sweep >= max_sweeps) { result = max_sweeps + 1; break; }
+#pragma unroll 1
+        for (int rr = 0; rr < N / 2; ++rr) {
+            jacobi_round_skew<N, SEGS, 0>(S, U, rows, cs2, lane);
+            jacobi_round_skew<N, SEGS, 1>(S, U, rows, cs2, lane);
+        }
+    }
+    // unskew S, then U, through LDS
+    wave_lds_sync();
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) myrow[base + k < N ? base + k : base + k - N] = S[k];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < N; ++k) S[k] = active ? myrow[k] : 0.0;
+    wave_lds_sync();
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) myrow[base + k < N ? base + k : base + k - N] = U[k];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < N; ++k) U[k] = active ? myrow[k] : 0.0;
+    wave_lds_sync();
+    return result;
+}
+
 // One node's cycle-diagnostics record from the group of G lanes (the whole
 // wavefront by default) that holds the node (lane = member, lanes >= M hold
 // nothing): the squared error of the

@@ -34,10 +34,11 @@ template <int N>
 struct EigLayout {
     static_assert(N >= 8 && N % 2 == 0, "eigenproblem size must be even and >= 8");
     static constexpr int SEGS = 64 / N;
-    static constexpr int RS = RowStride<N>::value;
+    static constexpr int RS = SkewStride<N>::value;  // the skewed-row Jacobi's stride
     // Jacobi rows (also the convergence partial sums between sweeps), then U
     static constexpr int kRows = SEGS * N * RS > 128 ? SEGS * N * RS : 128;
-    static constexpr int kVec = 3 * 64;  // (c, s) during Jacobi; psi t, phi, h after
+    // the duplicated (c, s) lists during Jacobi; psi t, phi, h after
+    static constexpr int kVec = 4 * 64;
     static constexpr int kObs = 2 * SEGS * N + (SEGS * N + 1) / 2;  // sw, dt, q
     static constexpr int total = kRows + kVec + kObs;
 };
@@ -109,7 +110,7 @@ __device__ __forceinline__ void eig_body(const AnalysisParams p, const int* node
             U[k] = (k == i && active) ? 1.0 : 0.0;
         }
     }
-    const int sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, rows, lane, p.max_sweeps);
+    const int sweeps = jacobi_eig_skew<N, SEGS>(S, U, rows, cs, lane, p.max_sweeps);
     if (sweeps > p.max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
 
     // eigenvalue functions, U to LDS, t = U^T d~, h = U psi t, G = U phi U^T
@@ -404,13 +405,12 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
 
 // Split rows above N = 32.  At N = 32 itself one wavefront holding two nodes
 // with whole rows beats one node with half rows in a wavefront (measured 103
-// against 134 ns per node at 64 members).  Up to N = 18 the eigensolver fits
-// in 168 VGPRs (three wavefronts per SIMD) without spilling; larger N keep the
-// compiler's choice (three up to N = 24).  Four wavefronts per SIMD (128
-// VGPRs: no spill inside the sweeps at N = 18, a few at N = 20 and 22) were
-// measured no faster at N = 18 and 2-4 % slower overall when extended to
-// N = 20 and 22: the sweeps are bound by the LDS traffic of the row exchange
-// and the rotation broadcast, not by latency.
+// against 134 ns per node at 64 members).  With skewed rows the eigensolver
+// fits in 128 VGPRs (four wavefronts per SIMD) up to N = 16 and in 168 (three)
+// up to N = 22 without spilling; N = 24 would spill 40 bytes per lane at three
+// and keeps two.  Four wavefronts per SIMD at N = 18-22 were measured no faster
+// (with plain rows): the rounds are held by the LDS traffic of the row
+// exchange and the rotation broadcast and by their latency, not by occupancy.
 template <int N>
 constexpr bool kSplitRows = N > 32;
 
@@ -418,7 +418,7 @@ template <int N>
 constexpr int eig_threads() { return kSplitRows<N> ? 2 * kWave : kWave; }
 
 template <int N>
-constexpr int eig_waves() { return N <= 18 ? 3 : 1; }
+constexpr int eig_waves() { return N <= 16 ? 4 : (N <= 22 ? 3 : 1); }
 
 template <int N>
 constexpr int eig_lds_doubles() {
