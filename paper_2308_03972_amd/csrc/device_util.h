@@ -246,18 +246,26 @@ __device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2*
 // (skewed) rows as before.  Every entry sees the same operations on the same
 // operands as in the unskewed solver, up to exact sign changes.
 // ---------------------------------------------------------------------------
-// Row stride (doubles) of a skewed published row: the N entries at 2..N+1 with
-// copies of registers N-2, N-1 at 0, 1 and of registers 0, 1 at N+2, N+3, so
-// that a partner's columns are read at a fixed offset; stride/2 odd.
+// Row stride (doubles) of a skewed published row: an odd lane's registers at
+// 0..N-1 (0, 1 again at N, N+1), an even lane's at 4..N+3 (N-2, N-1 again at
+// 2, 3), so that every partner reads at offset 2; stride/2 odd.
 template <int N>
 struct SkewStride {
     static constexpr int value = (N % 4 == 2) ? N + 4 : N + 6;
 };
 
-// (c, s) lists of the skewed solver: per segment 2N entries, entry j + N a
-// copy of entry j, so that lane i reads pair (b + k) at b + k without a wrap.
+// (c, s) lists of the skewed solver, one entry per pair: pair m of a round is
+// columns (2m + P, 2m + P + 1) (for P = 1, m = N/2 - 1 stands for the unpaired
+// columns N - 1, 0), and entry m + N/2 repeats entry m, so that register pair j
+// of a lane with base b reads entry b/2 + j without a wrap.  Segments start
+// skew_cs_stride(N) entries apart: with 16 lanes per LDS pass and 64 banks the
+// entries one read instruction touches then fall on distinct banks.
+__host__ __device__ constexpr int skew_cs_stride(int n) {
+    return n == 10 ? 21 : n == 14 ? 23 : n == 18 ? 25 : n == 20 ? 26 : n == 22 ? 29
+         : n == 24 ? 28 : n == 26 ? 29 : n == 28 ? 30 : n == 30 ? 31 : n == 12 ? 13 : n;
+}
 template <int N, int SEGS>
-__host__ __device__ constexpr int skew_cs_doubles() { return SEGS * 2 * N * 2; }
+__host__ __device__ constexpr int skew_cs_doubles() { return SEGS * skew_cs_stride(N) * 2; }
 
 template <int N, int SEGS, int P>
 __device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N], double* rows,
@@ -269,7 +277,8 @@ __device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N]
     const int sbase = active ? seg * N : 0;
     const bool odd = (i & 1) != 0;
     const int base = i - (i & 1);
-    double2* csl = cs2 + (size_t)(active ? seg : 0) * 2 * N;
+    double2* csl = cs2 + (size_t)(active ? seg : 0) * skew_cs_stride(N);
+    const int hb = base / 2;
     const bool first = ((i - P) & 1) == 0;
     double c, s;
     if constexpr (P == 0) {
@@ -283,9 +292,9 @@ __device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N]
         const double aqq = odd ? S[1] : x1;
         jacobi_rotation(app, aqq, apq, active, &c, &s);
         wave_lds_sync();
-        if (active) {
-            csl[i] = make_double2(c, s);
-            csl[i + N] = make_double2(c, s);
+        if (active && !odd) {
+            csl[i / 2] = make_double2(c, s);
+            csl[i / 2 + N / 2] = make_double2(c, s);
         }
         // row mix with the partner's row (same columns, same registers)
         const double sg = first ? s : -s;
@@ -299,7 +308,7 @@ __device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N]
         // (b + 2j, b + 2j + 1) mod N, an even first column
 #pragma unroll
         for (int j = 0; j < N / 2; ++j) {
-            const double2 q = csl[base + 2 * j];
+            const double2 q = csl[hb + j];
             const int r = 2 * j;
             const double a0 = S[r], a1 = S[r + 1];
             S[r] = q.y * a0 + q.x * a1;
@@ -311,48 +320,52 @@ __device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N]
     } else {
         double* segrows = rows + (size_t)sbase * RS;
         wave_lds_sync();
+        // Each lane publishes its row where its partner reads it at offset 2:
+        // column b + k of an odd lane's partner (base b + 2) is that lane's
+        // register k - 2, of an even lane's partner (base b - 2) its register
+        // k + 2.  So an odd lane stores register r at r (and registers 0, 1
+        // again at N, N + 1), an even lane at r + 4 (and registers N - 2, N - 1
+        // again at 2, 3).
         if (active) {
-            double2* my = reinterpret_cast<double2*>(segrows + (size_t)i * RS);
-            my[0] = make_double2(S[N - 2], S[N - 1]);
+            double2* my = reinterpret_cast<double2*>(segrows + (size_t)i * RS + (odd ? 0 : 4));
 #pragma unroll
-            for (int k = 0; k < N / 2; ++k) my[k + 1] = make_double2(S[2 * k], S[2 * k + 1]);
-            my[N / 2 + 1] = make_double2(S[0], S[1]);
+            for (int k = 0; k < N / 2; ++k) my[k] = make_double2(S[2 * k], S[2 * k + 1]);
+            *reinterpret_cast<double2*>(segrows + (size_t)i * RS + (odd ? N : 2)) =
+                odd ? make_double2(S[0], S[1]) : make_double2(S[N - 2], S[N - 1]);
         }
         wave_lds_sync();
         // pair (2m + 1, 2m + 2): a_pp, a_pq are the odd lane's registers 1, 2
-        // (stored at 3, 4), a_qq the even lane's register 0 (stored at 2); a lane
+        // (stored at 1, 2), a_qq the even lane's register 0 (stored at 4); a lane
         // without a partner reads the first pair's block and discards it
         const int pi = first ? i + 1 : i - 1;
         const bool paired = active && pi >= 0 && pi < N;
         const int p = paired ? (first ? i : pi) : 1;
-        // the partner's copy of this lane's column b + k: storage k for an odd
-        // lane (partner base b + 2), k + 4 for an even one (b - 2); a lane
-        // without a partner takes its own row (storage 2 + k) with c = 1, s = 0
+        // a lane without a partner reads its own row and keeps (lane 0:
+        // negates) its own values: coefficients (0, 1), (0, -1) below
         const int src = paired ? pi : (active ? i : 0);
-        const int off = paired ? (odd ? 0 : 4) : 2;
-        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)src * RS + off);
+        const double2* pr = reinterpret_cast<const double2*>(segrows + (size_t)src * RS + 2);
         constexpr int KP = N / 2 < 4 ? N / 2 : 4;
         double2 pre[KP];
 #pragma unroll
         for (int k = 0; k < KP; ++k) pre[k] = pr[k];
-        jacobi_rotation(segrows[(size_t)p * RS + 3], segrows[(size_t)(p + 1) * RS + 2],
-                        segrows[(size_t)p * RS + 4], paired, &c, &s);
+        jacobi_rotation(segrows[(size_t)p * RS + 1], segrows[(size_t)(p + 1) * RS + 4],
+                        segrows[(size_t)p * RS + 2], paired, &c, &s);
         // Columns N - 1 and 0, which no rotation pairs in this round, meet in
         // registers (N - 1 - b, N - b) of every lane, where the pair update
         // (which swaps as it rotates) runs on them too.  The list entry of
         // column N - 1, (c, s) = (0, 1), makes that update keep column N - 1
         // and negate column 0: S D, U D with D = diag(-1, 1, ..., 1).  Lane 0
-        // negates its row, which completes D S D, a similarity; the negations
+        // negates its row (below), which completes D S D, a similarity; the negations
         // are exact, so every entry keeps the magnitude the unskewed solver
         // gives it, and the eigenvectors change sign only.
-        if (active) {
+        if (active && odd) {
             const double2 q = i == N - 1 ? make_double2(0.0, 1.0) : make_double2(c, s);
-            csl[i] = q;
-            csl[i + N] = q;
+            csl[i / 2] = q;
+            csl[i / 2 + N / 2] = q;
         }
         wave_lds_sync();
-        const double sg = first ? s : -s;
-        const double cr = (active && i == 0) ? -1.0 : c;
+        const double cr = paired ? c : 0.0;
+        const double sg = paired ? (first ? s : -s) : ((active && i == 0) ? -1.0 : 1.0);
 #pragma unroll
         for (int k = 0; k < N / 2; ++k) {
             const double2 v = k < KP ? pre[k < KP ? k : 0] : pr[k];
@@ -364,7 +377,7 @@ __device__ __forceinline__ void jacobi_round_skew(double (&S)[N], double (&U)[N]
 #pragma unroll
         for (int j = 0; j < N / 2; ++j) {
             const int r0 = 2 * j + 1, r1 = (2 * j + 2) % N;
-            const double2 q = csl[base + r0];
+            const double2 q = csl[hb + j];
             const double a0 = S[r0], a1 = S[r1];
             S[r0] = q.y * a0 + q.x * a1;
             S[r1] = q.x * a0 - q.y * a1;

@@ -30,15 +30,23 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // eigen part: SEGS = 64 / N nodes per wavefront
 // ---------------------------------------------------------------------------
+// The Jacobi of the one-wavefront eigen kernels with skewed rows (P = 0 rounds
+// by DPP, device_util.h) where their larger LDS rows keep the occupancy the
+// registers allow; at N = 8, 12-16, 20 and 32 plain rows already fill, or
+// nearly fill, the LDS at that occupancy and stay.
+template <int N>
+constexpr bool kSkewRows = N == 10 || N == 18 || (N >= 22 && N <= 30);
+
 template <int N>
 struct EigLayout {
     static_assert(N >= 8 && N % 2 == 0, "eigenproblem size must be even and >= 8");
     static constexpr int SEGS = 64 / N;
-    static constexpr int RS = SkewStride<N>::value;  // the skewed-row Jacobi's stride
+    static constexpr int RS = kSkewRows<N> ? SkewStride<N>::value : RowStride<N>::value;
     // Jacobi rows (also the convergence partial sums between sweeps), then U
     static constexpr int kRows = SEGS * N * RS > 128 ? SEGS * N * RS : 128;
-    // the duplicated (c, s) lists during Jacobi; psi t, phi, h after
-    static constexpr int kVec = 4 * 64;
+    // (c, s) during Jacobi; psi t, phi, h after
+    static constexpr int kCs = kSkewRows<N> ? skew_cs_doubles<N, SEGS>() : 2 * 64;
+    static constexpr int kVec = kCs > 3 * 64 ? kCs : 3 * 64;
     static constexpr int kObs = 2 * SEGS * N + (SEGS * N + 1) / 2;  // sw, dt, q
     static constexpr int total = kRows + kVec + kObs;
 };
@@ -110,7 +118,9 @@ __device__ __forceinline__ void eig_body(const AnalysisParams p, const int* node
             U[k] = (k == i && active) ? 1.0 : 0.0;
         }
     }
-    const int sweeps = jacobi_eig_skew<N, SEGS>(S, U, rows, cs, lane, p.max_sweeps);
+    int sweeps;
+    if constexpr (kSkewRows<N>) sweeps = jacobi_eig_skew<N, SEGS>(S, U, rows, cs, lane, p.max_sweeps);
+    else sweeps = jacobi_eig<N, SEGS>(S, U, rows, cs, rows, lane, p.max_sweeps);
     if (sweeps > p.max_sweeps && lane == 0) atomicAdd(p.eig_fail, 1);
 
     // eigenvalue functions, U to LDS, t = U^T d~, h = U psi t, G = U phi U^T
@@ -405,11 +415,11 @@ __device__ __forceinline__ void eig_body_split(const AnalysisParams p, const int
 
 // Split rows above N = 32.  At N = 32 itself one wavefront holding two nodes
 // with whole rows beats one node with half rows in a wavefront (measured 103
-// against 134 ns per node at 64 members).  With skewed rows the eigensolver
-// fits in 128 VGPRs (four wavefronts per SIMD) up to N = 16 and in 168 (three)
-// up to N = 22 without spilling; N = 24 would spill 40 bytes per lane at three
-// and keeps two.  Four wavefronts per SIMD at N = 18-22 were measured no faster
-// (with plain rows): the rounds are held by the LDS traffic of the row
+// against 134 ns per node at 64 members).  The eigensolver fits in 128 VGPRs
+// (four wavefronts per SIMD) up to N = 16 and in 168 (three) up to N = 22
+// without spilling; N = 24 with skewed rows would spill 40 bytes per lane at
+// three and keeps two.  Four wavefronts per SIMD at N = 18-22 were measured no
+// faster (with plain rows): the rounds are held by the LDS traffic of the row
 // exchange and the rotation broadcast and by their latency, not by occupancy.
 template <int N>
 constexpr bool kSplitRows = N > 32;
