@@ -109,23 +109,23 @@ struct RowStride {
 // Rotation (c, s) that annihilates a_pq of the 2 x 2 block [[a_pp, a_pq], [a_pq, a_qq]]
 // (c = 1, s = 0 for a_pq = 0 or when `use` is false).
 // t = sgn(tau) / (|tau| + sqrt(1 + tau^2)),
-// tau = (a_qq - a_pp) / (2 a_pq), the smaller root of t^2 + 2 tau t - 1 = 0, is
-// evaluated in FP32 on operands scaled so that |a_pq| is near [1, 2): any t gives
-// an exactly orthogonal rotation through c and s below (FP64), and an
-// FP32-accurate t still removes all but ~1e-7 of a_pq, which the next sweeps
-// finish.  Branch-free: for a_pq = 0 the intermediate t is inf or NaN and the
-// final select discards it, so the three operand loads of a caller issue
-// together instead of waiting on a test of a_pq.
+// tau = (a_qq - a_pp) / (2 a_pq), the smaller root of t^2 + 2 tau t - 1 = 0:
+// tau from the hardware FP64 reciprocal of a_pq (no overflow or underflow
+// short of FP64's range), then t in FP32.  Any t gives an exactly orthogonal
+// rotation through c and s below (FP64), and an FP32-accurate t still removes
+// all but ~1e-7 of a_pq, which the next sweeps finish.  |tau| beyond FP32's
+// range converts to inf and gives t = 0 (a_pq negligible against a_qq - a_pp).
+// Branch-free: for a_pq = 0 the intermediate t is inf or NaN and the final
+// select discards it, so the three operand loads of a caller issue together
+// instead of waiting on a test of a_pq.
 __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, bool use,
                                                 double* cp, double* sp) {
     const double d = aqq - app;
-    const double sc = ldexp(1.0, -max(ilogb(apq), -1000));
-    const float af = (float)(apq * sc);
-    const float at = fabsf((float)(d * sc)) * 0.5f * __builtin_amdgcn_rcpf(fabsf(af));
+    const float tau = (float)(d * (0.5 * __builtin_amdgcn_rcp(apq)));
+    const float at = fabsf(tau);
     // |tau| + sqrt(1 + tau^2), or 2 |tau| where tau^2 would overflow
     const float den = at > 1e18f ? at + at : at + __builtin_amdgcn_sqrtf(1.0f + at * at);
-    float tf = __builtin_amdgcn_rcpf(den);
-    if ((d < 0.0) != (apq < 0.0)) tf = -tf;
+    const float tf = copysignf(__builtin_amdgcn_rcpf(den), tau);
     const double t = (double)tf;
     const double c = rsqrt(1.0 + t * t);
     const bool rot = use && apq != 0.0;
