@@ -145,3 +145,45 @@ def test_set_checks_validation():
         st, _ = _status(lambda: binding._check(binding.load().lbmletkf_set_checks(
             ctx.handle, bad[0], bad[1], bad[2])))
         assert st == -1, bad
+
+
+@pytest.mark.parametrize("cfg_name", ["paper", "precision"])
+def test_nan_stays_inside_the_localization_of_its_observation(cfg_name):
+    """A NaN in one member at an observed node reaches, through that
+    observation's perturbation, only the nodes whose local observation set
+    holds it (squared distance < (2 d_cut)^2, periodic, Sec. 3.2.2) and the
+    node itself; every other node -- also those sharing a wavefront, a
+    segment pass or a batch of LDS reads with an affected node in the eigen
+    and apply kernels -- stays finite and keeps the clean run's analysis to
+    rounding: a wavefront sweeps until all of its nodes converge, so a node
+    beside a NaN node takes the sweep cap's further (vanishing) rotations."""
+    cfg = inputs.CONFIGS[cfg_name]
+    say(f"checks: NaN localization {cfg_name}")
+    _, fe = config_state(cfg)
+    ctx = context(cfg)
+    pts = inputs.observation_points(cfg)
+    x0, y0 = (int(v) for v in pts[len(pts) // 2])
+    fe_nan = fe.copy()
+    fe_nan[3, 0, y0, x0] = float("nan")        # rest population: stays at (x0, y0)
+    outs, yo = [], None
+    for canon in (fe, fe_nan):
+        f = ctx.import_canonical(cuda(canon))
+        yf = ctx.observe(f)
+        if yo is None:                          # the same observations for both runs
+            yo = (yf.mean(dim=0) + 1e-3).contiguous()
+        ctx.analyze(f, yf, yo)
+        outs.append(host(ctx.export_canonical(f)))
+    clean, dirty = outs
+    assert np.isfinite(clean).all()
+    changed = ~(dirty == clean).all(axis=(0, 1))   # [y][x]
+    dev = np.nan_to_num(np.abs(dirty - clean), nan=np.inf).max(axis=(0, 1))
+    n = cfg.n
+    ys, xs = np.mgrid[0:n, 0:n]
+    dx = np.minimum(np.abs(xs - x0), n - np.abs(xs - x0))
+    dy = np.minimum(np.abs(ys - y0), n - np.abs(ys - y0))
+    inside = (dx * dx + dy * dy) < 4.0 * cfg.d_cut ** 2
+    say(f"  changed nodes {int(changed.sum())}, inside the support {int(inside.sum())}")
+    say(f"  outside: changed {int((changed & ~inside).sum())}, max |diff| {dev[~inside].max():.2e}")
+    assert changed[y0, x0] and not np.isfinite(dirty[:, :, y0, x0]).all()
+    assert np.isfinite(dirty[:, :, ~inside]).all()
+    assert dev[~inside].max() <= 1e-14
