@@ -366,6 +366,12 @@ typedef struct {
                                    over every problem's (6 x 6 tile, 16-member group) blocks, the
                                    first step's results kept on chip (needs 16 | members in every
                                    problem; the same bits as single steps) */
+    int32_t analysis_queue;     /* 0: per observation-route group one eigen and one apply launch
+                                   with a block per (problem, node tile) item; 1: persistent
+                                   launches (16 wavefronts per CU) whose blocks take the items
+                                   from per-XCD queues in the batch workspace, four at a time;
+                                   the same bits (measured ~4x slower on the twelve-problem
+                                   batch: the loop costs the eigen kernels occupancy) */
 } lbmletkf_batch_config;
 
 lbmletkf_status lbmletkf_batch_workspace_bytes(lbmletkf_ctx* const* ctxs, int32_t n, size_t* bytes);
@@ -373,7 +379,7 @@ lbmletkf_status lbmletkf_batch_workspace_bytes(lbmletkf_ctx* const* ctxs, int32_
 /* Create a batch of n contexts with states d_f[k] (device, storage layout) and
  * nsteps forecast steps per cycle.  ctxs and d_f are host arrays of n pointers.
  * cfg may be NULL: {one block per tile, 4 tile rows, granularity 2, graph, two steps per
- * launch where every problem allows it, else one}.  Waits for its setup copies and,
+ * launch where every problem allows it, else one, no analysis queue}.  Waits for its setup copies and,
  * with use_graph, captures the cycle. */
 lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_f, int32_t n,
                                       int32_t nsteps, const lbmletkf_batch_config* cfg,
@@ -393,8 +399,8 @@ lbmletkf_status lbmletkf_batch_set_config(lbmletkf_batch* batch, const lbmletkf_
 
 /* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048, 0}) x
  * (tile_rows in {1, 2, 4, 8}) forecast step, the two-step launch (per step, when
- * every problem allows it) and every bucket granularity
- * {2, 4, 8} of the analysis (reps timed runs each, HIP events), then applies
+ * every problem allows it) and every bucket granularity {2, 4, 8} x
+ * analysis_queue {0, 1} of the analysis (reps timed runs each, HIP events), then applies
  * the fastest with use_graph = 1.  Runs on the contexts' ping-pong partner
  * buffers: the bound states are not modified.  Outputs (any may be NULL): the
  * chosen configuration, its forecast ms per step and analysis ms per cycle. */

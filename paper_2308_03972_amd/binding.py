@@ -47,7 +47,7 @@ class ObsParams(ctypes.Structure):
 class BatchConfig(ctypes.Structure):
     _fields_ = [("forecast_blocks", _c_int32), ("tile_rows", _c_int32),
                 ("bucket_granularity", _c_int32), ("use_graph", _c_int32),
-                ("steps_per_launch", _c_int32)]
+                ("steps_per_launch", _c_int32), ("analysis_queue", _c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -1183,6 +1183,7 @@ struct Batch {
     std::vector<size_t> yo_off;
     char* gbase = nullptr;  // group region
     size_t gcap = 0;
+    int* d_queue = nullptr;  // [16 per group] work-queue counters (analysis_queue = 1)
     std::vector<BatchGroup> groups;
     int ntiles = 0;
     int nblocks2 = 0;  // blocks of a batched two-step launch
@@ -1198,8 +1199,12 @@ struct Batch {
 Batch* as_batch(lbmletkf_batch* b) { return reinterpret_cast<Batch*>(b); }
 
 struct BatchLayout {
-    size_t params, tasks, yo, groups, total, group_bytes;
+    size_t params, tasks, yo, queue, groups, total, group_bytes;
 };
+
+// Work-queue counters of the batched analysis: 16 per group, at most one group
+// per (route, eigenproblem size <= 64).
+constexpr int kQueueInts = 16 * 2 * 65;
 
 BatchLayout batch_layout(const std::vector<Ctx*>& ctx) {
     BatchLayout L{};
@@ -1225,6 +1230,7 @@ BatchLayout batch_layout(const std::vector<Ctx*>& ctx) {
     L.params = take(2 * n * sizeof(AnalysisParams));
     L.tasks = take(3 * n * sizeof(LbmTask));
     L.yo = take(nobs * sizeof(double));
+    L.queue = take(kQueueInts * sizeof(int));
     // groups: node lists, eigen waves, apply/ensemble waves, G buffers (+ alignment slack
     // for up to 64 groups of four arrays)
     L.group_bytes = nodes * (sizeof(int) + sizeof(int4) + sizeof(int2)) + gdoubles * sizeof(double) +
@@ -1365,6 +1371,8 @@ lbmletkf_status batch_groups(Batch* b, hipStream_t s) {
         }
     }
     if (off > b->gcap) return fail(LBMLETKF_EWORKSPACE, "batch workspace too small for its groups");
+    if (16 * b->groups.size() > (size_t)kQueueInts)
+        return fail(LBMLETKF_EUNSUPPORTED, "more analysis groups than work-queue counters");
     for (const NodeCopy& nc : node_copies) {
         e = hipMemcpyAsync(nc.dst, nc.src, nc.count * sizeof(int), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "batch node lists");
@@ -1407,13 +1415,20 @@ hipError_t batch_analysis(Batch* b, const AnalysisParams* params, hipStream_t s)
     bool used[Batch::kSide] = {false, false, false};
     for (const BatchGroup& grp : b->groups)
         if (grp.stream > 0) used[grp.stream - 1] = true;
-    hipError_t e = hipEventRecord(b->fork, s);
+    const bool queue = b->cfg.analysis_queue == 1;
+    hipError_t e = queue ? launch_zero_ints(b->d_queue, 16 * (int)b->groups.size(), s) : hipSuccess;
+    if (e == hipSuccess) e = hipEventRecord(b->fork, s);
     for (int k = 0; k < Batch::kSide && e == hipSuccess; ++k)
         if (used[k]) e = hipStreamWaitEvent(b->side[k], b->fork, 0);
     for (const BatchGroup& grp : b->groups) {
         if (e != hipSuccess) break;
         hipStream_t sk = grp.stream == 0 ? s : b->side[grp.stream - 1];
-        if (grp.route == LBMLETKF_ROUTE_OBSERVATION)
+        if (grp.route == LBMLETKF_ROUTE_OBSERVATION && queue)
+            e = launch_analysis_obs_batch_queue(params, grp.eig_waves, grp.n_eig, grp.waves,
+                                                grp.n_waves, grp.nodes, grp.n, grp.gbuf,
+                                                b->storage, b->mfma_transform,
+                                                b->d_queue + 16 * (&grp - b->groups.data()), sk);
+        else if (grp.route == LBMLETKF_ROUTE_OBSERVATION)
             e = launch_analysis_obs_batch(params, grp.eig_waves, grp.n_eig, grp.waves, grp.n_waves,
                                           grp.nodes, grp.n, grp.gbuf, b->storage,
                                           b->mfma_transform, sk);
@@ -1516,6 +1531,8 @@ lbmletkf_status batch_check_config(const lbmletkf_batch_config* cfg) {
         return fail(LBMLETKF_EINVAL, "bucket_granularity must be 2, 4 or 8");
     if (cfg->steps_per_launch != 1 && cfg->steps_per_launch != 2)
         return fail(LBMLETKF_EINVAL, "steps_per_launch must be 1 or 2");
+    if (cfg->analysis_queue != 0 && cfg->analysis_queue != 1)
+        return fail(LBMLETKF_EINVAL, "analysis_queue must be 0 or 1");
     return LBMLETKF_OK;
 }
 
@@ -1554,7 +1571,7 @@ lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_
     if (nsteps < 1) return fail(LBMLETKF_EINVAL, "nsteps must be >= 1");
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
         return fail(LBMLETKF_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-    lbmletkf_batch_config c0{0, 4, 2, 1, 1};
+    lbmletkf_batch_config c0{0, 4, 2, 1, 1, 0};
     const lbmletkf_batch_config* use = cfg ? cfg : &c0;
     lbmletkf_status st = batch_check_config(use);
     if (st) return st;
@@ -1590,6 +1607,7 @@ lbmletkf_status lbmletkf_batch_create(lbmletkf_ctx* const* ctxs, void* const* d_
     b->d_tasks[1] = b->d_tasks[0] + n;
     b->d_tasks[2] = b->d_tasks[0] + 2 * n;
     b->d_yo = reinterpret_cast<double*>(b->ws + L.yo);
+    b->d_queue = reinterpret_cast<int*>(b->ws + L.queue);
     b->gbase = b->ws + L.groups;
     b->gcap = L.group_bytes;
     size_t yo = 0;
@@ -1732,18 +1750,24 @@ lbmletkf_status lbmletkf_batch_tune(lbmletkf_batch* batch, int32_t reps, lbmletk
         e = hipMemcpyAsync(b->ctx[k]->fbuf(), b->f[k], b->ctx[k]->state_bytes(),
                            hipMemcpyDeviceToDevice, s);
     const int grans[] = {2, 4, 8};
+    const lbmletkf_batch_config fc = best_cfg;
     for (int g : grans) {
-        if (e != hipSuccess || st) break;
-        cur = best_cfg;
-        cur.bucket_granularity = g;
-        b->cfg = cur;
-        if ((st = batch_groups(b, s))) break;
-        double ms = 0.0;
-        e = batch_observe(b, true, s);
-        if (e == hipSuccess) e = timed([&]() { return batch_analysis(b, b->d_params_tune, s); }, &ms);
-        if (e == hipSuccess && ms < best_a) {
-            best_a = ms;
-            best_cfg.bucket_granularity = g;
+        for (int q = 0; q <= 1; ++q) {
+            if (e != hipSuccess || st) break;
+            cur = fc;
+            cur.bucket_granularity = g;
+            cur.analysis_queue = q;
+            b->cfg = cur;
+            if ((st = batch_groups(b, s))) break;
+            double ms = 0.0;
+            e = batch_observe(b, true, s);
+            if (e == hipSuccess)
+                e = timed([&]() { return batch_analysis(b, b->d_params_tune, s); }, &ms);
+            if (e == hipSuccess && ms < best_a) {
+                best_a = ms;
+                best_cfg.bucket_granularity = g;
+                best_cfg.analysis_queue = q;
+            }
         }
     }
     if (t0) (void)hipEventDestroy(t0);

@@ -226,6 +226,14 @@ hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4*
                                      int n_eig, const int2* d_apply_waves, int n_apply,
                                      const int* d_nodes, int n, double* gbuf, int storage,
                                      bool mfma_transform, hipStream_t s);
+// The same with persistent launches that take the wave lists' entries from
+// queues: counters[0..7] (eigen) and counters[8..15] (apply), zero on entry.
+hipError_t launch_analysis_obs_batch_queue(const AnalysisParams* d_params, const int4* d_eig_waves,
+                                           int n_eig, const int2* d_apply_waves, int n_apply,
+                                           const int* d_nodes, int n, double* gbuf, int storage,
+                                           bool mfma_transform, int* counters, hipStream_t s);
+// Zero n ints with a kernel (capturable in a graph, unlike hipMemsetAsync).
+hipError_t launch_zero_ints(int* v, int n, hipStream_t s);
 int diag_blocks_for(int plane);
 // Bytes of diag_partial_kernel's per-block records for a grid of `plane` nodes.
 size_t diag_partial_bytes(int plane);

@@ -878,6 +878,83 @@ __global__ __launch_bounds__(64) void analysis_apply_batch_kernel(const Analysis
     apply_node<N, T, MF>(p, nodes, d.y, gin);
 }
 
+// Work-queue form of the batched kernels: a persistent grid whose blocks take
+// entries of the group's wave list from queues in device memory until they are
+// exhausted.  The list is cut into eight contiguous ranges, one per XCD (block
+// b runs on XCD b mod 8), each with its own counter that a block advances by
+// kQueueChunk entries with one lane's vector atomic add: one counter for the
+// whole device would serialise every block's add across the XCDs.  Every block
+// leaves once its counter has passed the end of its range; each entry is
+// processed exactly as in the one-launch-per-wave form.
+constexpr int kQueueChunk = 4;
+
+__device__ __forceinline__ int queue_take(int* counters, int* next, int lo) {
+    __syncthreads();  // the previous entries' LDS use ends before `next` is rewritten
+    if (threadIdx.x == 0) *next = lo + atomicAdd(counters + blockIdx.x % 8, kQueueChunk);
+    __syncthreads();
+    return *next;
+}
+
+template <int N>
+__global__ __launch_bounds__(eig_threads<N>()) __attribute__((amdgpu_waves_per_eu(eig_waves<N>())))
+void analysis_eig_queue_kernel(const AnalysisParams* P, const int4* waves, int nwaves,
+                               const int* nodes, double* gout, int* counters) {
+    __shared__ int next;
+    const int per = (nwaves + 7) / 8;
+    const int lo = (int)(blockIdx.x % 8) * per;
+    const int hi = min(nwaves, lo + per);
+    for (;;) {
+        const int w0 = queue_take(counters, &next, lo);
+        if (w0 >= hi) return;  // uniform over the block
+        const int w1 = min(hi, w0 + kQueueChunk);
+        for (int w = w0; w < w1; ++w) {
+            if (w > w0) __syncthreads();
+            const int4 d = waves[w];
+            const AnalysisParams p = P[d.x];
+            if constexpr (kSplitRows<N>) eig_body_split<N>(p, nodes, d.y, d.z, gout);
+            else eig_body<N>(p, nodes, d.y, d.z, gout);
+        }
+    }
+}
+
+template <int N, typename T, bool MF>
+__global__ __launch_bounds__(64) void analysis_apply_queue_kernel(const AnalysisParams* P,
+                                                                  const int2* waves, int nwaves,
+                                                                  const int* nodes,
+                                                                  const double* __restrict__ gin,
+                                                                  int* counters) {
+    __shared__ int next;
+    const int per = (nwaves + 7) / 8;
+    const int lo = (int)(blockIdx.x % 8) * per;
+    const int hi = min(nwaves, lo + per);
+    for (;;) {
+        const int w0 = queue_take(counters, &next, lo);
+        if (w0 >= hi) return;
+        const int w1 = min(hi, w0 + kQueueChunk);
+        for (int w = w0; w < w1; ++w) {
+            if (w > w0) __syncthreads();
+            const int2 d = waves[w];
+            const AnalysisParams p = P[d.x];
+            apply_node<N, T, MF>(p, nodes, d.y, gin);
+        }
+    }
+}
+
+// Blocks of a persistent launch: enough wavefronts to fill every CU (16 per CU,
+// the most any of these kernels keeps resident), at most `items`; blocks
+// beyond what fits start later and find the queue drained or nearly so.
+inline int persistent_blocks(int threads, int items) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    const int g = cus * 16 * 64 / threads;  // a multiple of 8: every XCD range has blocks
+    return g < items ? g : items;           // items < g: one block per entry
+}
+
 template <int N>
 hipError_t launch_n(const AnalysisParams& p, const int* nodes, int count, double* gbuf,
                     hipStream_t s) {
@@ -927,6 +1004,34 @@ hipError_t launch_batch_n(const AnalysisParams* d_params, const int4* d_eig_wave
     return hipGetLastError();
 }
 
+template <int N>
+hipError_t launch_batch_queue_n(const AnalysisParams* d_params, const int4* d_eig_waves, int n_eig,
+                                const int2* d_apply_waves, int n_apply, const int* d_nodes,
+                                double* gbuf, int storage, bool mfma_transform, int* counters,
+                                hipStream_t s) {
+    if (n_eig == 0) return hipSuccess;
+    const size_t eig_bytes = (size_t)eig_lds_doubles<N>() * sizeof(double);
+    static bool lds_ok = false;
+    hipError_t e = allow_lds(analysis_eig_queue_kernel<N>, eig_bytes, &lds_ok);
+    if (e != hipSuccess) return e;
+    const int ge = persistent_blocks(eig_threads<N>(), n_eig);
+    analysis_eig_queue_kernel<N><<<ge, eig_threads<N>(), eig_bytes, s>>>(
+        d_params, d_eig_waves, n_eig, d_nodes, gbuf, counters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t app_bytes = (size_t)apply_lds_doubles(N) * sizeof(double);
+    auto go = [&](auto kernel) {
+        const int ga = persistent_blocks(64, n_apply);
+        kernel<<<ga, 64, app_bytes, s>>>(d_params, d_apply_waves, n_apply, d_nodes, gbuf,
+                                         counters + 8);
+        return hipGetLastError();
+    };
+    if (storage == kStoreF32Dev && mfma_transform && kMfmaApply<N>)
+        return go(analysis_apply_queue_kernel<N, float, true>);
+    if (storage == kStoreF32Dev) return go(analysis_apply_queue_kernel<N, float, false>);
+    return go(analysis_apply_queue_kernel<N, double, false>);
+}
+
 }  // namespace
 
 #define LBMLETKF_OBS_SIZES(X) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) \
@@ -966,7 +1071,34 @@ hipError_t launch_analysis_obs(const AnalysisParams& p, const int* nodes, int co
     }
 }
 
+namespace {
+__global__ void zero_ints_kernel(int* v, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = 0;
+}
+}  // namespace
+
+hipError_t launch_zero_ints(int* v, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    zero_ints_kernel<<<1, 256, 0, s>>>(v, n);
+    return hipGetLastError();
+}
+
 int obs_segments(int n) { return n > 0 ? 64 / n : 0; }
+
+hipError_t launch_analysis_obs_batch_queue(const AnalysisParams* d_params, const int4* d_eig_waves,
+                                           int n_eig, const int2* d_apply_waves, int n_apply,
+                                           const int* d_nodes, int n, double* gbuf, int storage,
+                                           bool mfma_transform, int* counters, hipStream_t s) {
+    switch (n) {
+#define X(v)                                                                                \
+    case v:                                                                                 \
+        return launch_batch_queue_n<v>(d_params, d_eig_waves, n_eig, d_apply_waves, n_apply, \
+                                       d_nodes, gbuf, storage, mfma_transform, counters, s);
+        LBMLETKF_OBS_SIZES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_analysis_obs_batch(const AnalysisParams* d_params, const int4* d_eig_waves,
                                      int n_eig, const int2* d_apply_waves, int n_apply,

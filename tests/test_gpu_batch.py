@@ -130,6 +130,28 @@ def test_batch_two_step_launches_reproduce_run_cycle(storage):
             assert np.array_equal(s_, b_)
 
 
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_batch_analysis_work_queue_reproduces_run_cycle(storage):
+    """analysis_queue = 1: persistent eigen and apply launches whose blocks take
+    the (problem, node tile) items from a queue; each problem's states equal its
+    own run_cycle bit for bit, graph (the counters cleared by a kernel inside
+    it) and eager, over three cycles."""
+    say(f"batch analysis work queue storage={storage}")
+    base = inputs.CONFIGS["tiny"]
+    # plus a problem whose every node sees all 50 observations: the split-row
+    # eigen kernel (N = 56, two wavefronts per block) through the queue
+    cfgs = _mixed_configs() + [base.replace(name="b4", n=20, members=64, obs_side=5, loc_r=0.0,
+                                            seed=14)]
+    probs = _setup(cfgs, storage, cycles=3)
+    single = _single_runs(probs, 3)
+    for graph in (1, 0):
+        batched = _batch_runs(probs, 3, config=dict(forecast_blocks=0, tile_rows=2,
+                                                    bucket_granularity=2, use_graph=graph,
+                                                    steps_per_launch=1, analysis_queue=1))
+        for s_, b_ in zip(single, batched):
+            assert np.array_equal(s_, b_)
+
+
 def test_batch_graph_replays_match_eager_launches():
     """Three cycles replayed from the captured graph against the same cycles
     issued launch by launch, compared after every cycle."""
