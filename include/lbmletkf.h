@@ -399,8 +399,8 @@ lbmletkf_status lbmletkf_batch_set_config(lbmletkf_batch* batch, const lbmletkf_
 
 /* Autotuner: times every (forecast_blocks in {256, 512, 1024, 2048, 0}) x
  * (tile_rows in {1, 2, 4, 8}) forecast step, the two-step launch (per step, when
- * every problem allows it) and every bucket granularity {2, 4, 8} x
- * analysis_queue {0, 1} of the analysis (reps timed runs each, HIP events), then applies
+ * every problem allows it) and every bucket granularity {2, 4, 8} of the analysis
+ * (reps timed runs each, HIP events; analysis_queue keeps its setting), then applies
  * the fastest with use_graph = 1.  Runs on the contexts' ping-pong partner
  * buffers: the bound states are not modified.  Outputs (any may be NULL): the
  * chosen configuration, its forecast ms per step and analysis ms per cycle. */

@@ -1749,25 +1749,21 @@ lbmletkf_status lbmletkf_batch_tune(lbmletkf_batch* batch, int32_t reps, lbmletk
     for (size_t k = 0; k < b->ctx.size() && e == hipSuccess && !st; ++k)
         e = hipMemcpyAsync(b->ctx[k]->fbuf(), b->f[k], b->ctx[k]->state_bytes(),
                            hipMemcpyDeviceToDevice, s);
+    // (the work-queue form keeps the batch's current setting: it measured about
+    // four times slower than one launch per group, so timing it is wasted here)
     const int grans[] = {2, 4, 8};
-    const lbmletkf_batch_config fc = best_cfg;
     for (int g : grans) {
-        for (int q = 0; q <= 1; ++q) {
-            if (e != hipSuccess || st) break;
-            cur = fc;
-            cur.bucket_granularity = g;
-            cur.analysis_queue = q;
-            b->cfg = cur;
-            if ((st = batch_groups(b, s))) break;
-            double ms = 0.0;
-            e = batch_observe(b, true, s);
-            if (e == hipSuccess)
-                e = timed([&]() { return batch_analysis(b, b->d_params_tune, s); }, &ms);
-            if (e == hipSuccess && ms < best_a) {
-                best_a = ms;
-                best_cfg.bucket_granularity = g;
-                best_cfg.analysis_queue = q;
-            }
+        if (e != hipSuccess || st) break;
+        cur = best_cfg;
+        cur.bucket_granularity = g;
+        b->cfg = cur;
+        if ((st = batch_groups(b, s))) break;
+        double ms = 0.0;
+        e = batch_observe(b, true, s);
+        if (e == hipSuccess) e = timed([&]() { return batch_analysis(b, b->d_params_tune, s); }, &ms);
+        if (e == hipSuccess && ms < best_a) {
+            best_a = ms;
+            best_cfg.bucket_granularity = g;
         }
     }
     if (t0) (void)hipEventDestroy(t0);
