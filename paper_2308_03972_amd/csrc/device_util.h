@@ -242,9 +242,10 @@ __device__ int jacobi_eig(double (&S)[N], double (&U)[N], double* rows, double2*
 // columns in the same registers, and a_pp, a_pq, a_qq of their 2 x 2 block sit
 // in registers 0 and 1, so a P = 0 round takes the partner's row and the block
 // by DPP quad permutations instead of through LDS; only the rotations (c, s)
-// go through LDS, to every lane of the segment.  P = 1 rounds publish the
-// (skewed) rows as before.  Every entry sees the same operations on the same
-// operands as in the unskewed solver, up to exact sign changes.
+// go through LDS, to every lane of the segment.  P = 1 rounds publish each
+// row through LDS where its partner reads it.  Every entry sees the same
+// operations on the same operands as in the unskewed solver, up to exact sign
+// changes.
 // ---------------------------------------------------------------------------
 // Row stride (doubles) of a skewed published row: an odd lane's registers at
 // 0..N-1 (0, 1 again at N, N+1), an even lane's at 4..N+3 (N-2, N-1 again at
@@ -259,7 +260,8 @@ struct SkewStride {
 // columns N - 1, 0), and entry m + N/2 repeats entry m, so that register pair j
 // of a lane with base b reads entry b/2 + j without a wrap.  Segments start
 // skew_cs_stride(N) entries apart: with 16 lanes per LDS pass and 64 banks the
-// entries one read instruction touches then fall on distinct banks.
+// entries the active lanes of one read instruction touch then fall on distinct
+// banks.
 __host__ __device__ constexpr int skew_cs_stride(int n) {
     return n == 10 ? 21 : n == 14 ? 23 : n == 18 ? 25 : n == 20 ? 26 : n == 22 ? 29
          : n == 24 ? 28 : n == 26 ? 29 : n == 28 ? 30 : n == 30 ? 31 : n == 12 ? 13 : n;
